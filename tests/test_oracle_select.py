@@ -1,0 +1,199 @@
+"""Pins of the oracle's node selection against Eq. (1): the weighted reservoir
+sampling of Alg. 4 with logarithmic keys must pick node j with probability
+w_j / sum(w) (the A-Res property, Sec. 4.2.2), over the unvisited part of the
+candidate list (Sec. 4.3), or over every unvisited node when none is left.
+Exact probabilities are computed here in float64 straight from d and tau."""
+import itertools
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_2003_11902_amd import instances as I
+
+DRAWS = 120_000
+
+
+def chi2_ok(counts: dict, probs: dict, draws: int, pmin=1e-3):
+    keys = sorted(probs)
+    obs = np.array([counts.get(k, 0) for k in keys], dtype=np.float64)
+    exp = np.array([probs[k] for k in keys]) * draws
+    # never a node outside the support
+    assert sum(counts.values()) == obs.sum() == draws, "selected a node with zero probability"
+    # pool bins with small expectation into one
+    small = exp < 5
+    if small.any():
+        obs = np.append(obs[~small], obs[small].sum())
+        exp = np.append(exp[~small], exp[small].sum())
+    p = stats.chisquare(obs, exp).pvalue
+    assert p > pmin, (p, obs, exp)
+
+
+def ref_candidates(dist, cl):
+    n = dist.shape[0]
+    out = np.zeros((n, cl), dtype=np.int64)
+    for i in range(n):
+        js = np.array([j for j in range(n) if j != i])
+        order = np.lexsort((js, dist[i, js]))  # by distance, then index
+        out[i] = js[order][:cl]
+    return out
+
+
+def sample(col, cur, visited, draws=DRAWS, step=5):
+    counts = {}
+    fbs = set()
+    for a in range(draws):
+        v, fb = col.select_next(cur, visited, 11, a, step)
+        counts[v] = counts.get(v, 0) + 1
+        fbs.add(fb)
+    return counts, fbs
+
+
+@pytest.fixture(scope="module")
+def inst():
+    _, d = I.make_instance("uniform", 24, seed=4)
+    return d
+
+
+def test_candidates_match_sorted_rows(orc, inst):
+    col = orc.Colony(inst, ants=1, cand_len=6)
+    assert np.array_equal(col.cand().astype(np.int64), ref_candidates(inst, 6))
+    assert np.array_equal(orc.nearest(inst, 23).astype(np.int64), ref_candidates(inst, 23))
+
+
+@pytest.mark.parametrize("kind", ["random", "geometric", "dominant"])
+def test_candidate_phase_frequencies(orc, inst, kind):
+    n, cl = inst.shape[0], 8
+    col = orc.Colony(inst, ants=1, cand_len=cl, alpha=1, beta=2, seed=2024)
+    rng = np.random.default_rng(5)
+    if kind == "random":
+        tau = rng.uniform(0.1, 1.0, size=(n, n))
+    elif kind == "geometric":
+        tau = 0.5 ** rng.integers(0, 12, size=(n, n)).astype(np.float64)
+    else:
+        tau = np.full((n, n), 1e-3)
+    cur = 3
+    cands = ref_candidates(inst, cl)[cur]
+    if kind == "dominant":
+        tau[cur, cands[5]] = 3.0  # one edge far above the others
+    col.set_pheromone(tau.astype(np.float32))
+    col.prepare_choice()
+    visited = np.zeros(n, np.uint8)
+    visited[[cur, cands[0], cands[3]]] = 1
+    w = {int(j): float(np.float32(tau[cur, j])) * (1.0 / inst[cur, j]) ** 2
+         for j in cands if not visited[j]}
+    tot = sum(w.values())
+    counts, fbs = sample(col, cur, visited)
+    assert fbs == {False}
+    chi2_ok(counts, {k: v / tot for k, v in w.items()}, DRAWS)
+
+
+def test_fallback_frequencies_dense(orc, inst):
+    n, cl = inst.shape[0], 4
+    col = orc.Colony(inst, ants=1, cand_len=cl, alpha=1, beta=2, seed=77)
+    rng = np.random.default_rng(6)
+    tau = rng.uniform(0.05, 1.0, size=(n, n)).astype(np.float32)
+    col.set_pheromone(tau)
+    col.prepare_choice()
+    cur = 10
+    cands = ref_candidates(inst, cl)[cur]
+    visited = np.zeros(n, np.uint8)
+    visited[cur] = 1
+    visited[cands] = 1
+    visited[[0, 1, 2, 17]] = 1
+    w = {j: float(tau[cur, j]) * (1.0 / inst[cur, j]) ** 2 for j in range(n) if not visited[j]}
+    tot = sum(w.values())
+    counts, fbs = sample(col, cur, visited)
+    assert fbs == {True}
+    chi2_ok(counts, {k: v / tot for k, v in w.items()}, DRAWS)
+
+
+def test_fallback_frequencies_candidate_mode(orc, inst):
+    """Candidate-only trails: the fallback weight of an edge off the lists is
+    tau_min^alpha * eta^beta."""
+    n, cl = inst.shape[0], 4
+    col = orc.Colony(inst, ants=1, cand_len=cl, alpha=2, beta=3, seed=5,
+                     pher_mode=orc.PHER_CANDIDATES)
+    col.prepare_choice()
+    tmin, _ = col.limits()
+    cur = 7
+    cands = ref_candidates(inst, cl)[cur]
+    visited = np.zeros(n, np.uint8)
+    visited[cur] = 1
+    visited[cands] = 1
+    w = {j: float(tmin) ** 2 * (1.0 / inst[cur, j]) ** 3 for j in range(n) if not visited[j]}
+    tot = sum(w.values())
+    counts, fbs = sample(col, cur, visited)
+    assert fbs == {True}
+    chi2_ok(counts, {k: v / tot for k, v in w.items()}, DRAWS)
+
+
+def test_alpha_beta_zero_is_uniform(orc, inst):
+    n = inst.shape[0]
+    col = orc.Colony(inst, ants=1, cand_len=0, alpha=0, beta=0, seed=3)
+    col.prepare_choice()
+    visited = np.zeros(n, np.uint8)
+    visited[[0, 5, 6, 9]] = 1
+    free = [j for j in range(n) if not visited[j]]
+    counts, fbs = sample(col, 5, visited)
+    assert fbs == {True}
+    chi2_ok(counts, {j: 1.0 / len(free) for j in free}, DRAWS)
+
+
+def test_equal_keys_go_to_lowest_node(orc, inst):
+    """With every weight zero all keys are -inf and tie; the lowest node wins,
+    in the candidate phase and in the fallback."""
+    n, cl = inst.shape[0], 6
+    col = orc.Colony(inst, ants=1, cand_len=cl, seed=1)
+    col.set_pheromone(np.zeros((n, n), np.float32))
+    col.prepare_choice()
+    cur = 2
+    cands = ref_candidates(inst, cl)[cur]
+    visited = np.zeros(n, np.uint8)
+    visited[cur] = 1
+    visited[min(cands)] = 1
+    for a in range(50):
+        v, fb = col.select_next(cur, visited, 0, a, 1)
+        assert not fb and v == min(j for j in cands if not visited[j])
+    visited[cands] = 1
+    for a in range(50):
+        v, fb = col.select_next(cur, visited, 0, a, 1)
+        assert fb and v == min(j for j in range(n) if not visited[j])
+
+
+def exact_tour_probs(dist, tau, cl, alpha, beta):
+    """P(tour) = (1/n) * prod over steps of Eq. (1) restricted as in Sec. 4.3."""
+    n = dist.shape[0]
+    cands = ref_candidates(dist, cl)
+    w = tau.astype(np.float64) ** alpha * (1.0 / np.where(dist > 0, dist, 1)) ** beta
+    probs = {}
+    for perm in itertools.permutations(range(n)):
+        p = 1.0 / n
+        vis = {perm[0]}
+        for k in range(1, n):
+            c = perm[k - 1]
+            S = [j for j in cands[c] if j not in vis]
+            if not S:
+                S = [j for j in range(n) if j not in vis]
+            p *= (w[c, perm[k]] / sum(w[c, j] for j in S)) if perm[k] in S else 0.0
+            vis.add(perm[k])
+        if p > 0:
+            probs[perm] = p
+    assert abs(sum(probs.values()) - 1.0) < 1e-9
+    return probs
+
+
+@pytest.mark.parametrize("n,cl", [(5, 2), (6, 3)])
+def test_whole_tour_distribution_brute_force(orc, n, cl):
+    _, d = I.make_instance("uniform", n, seed=40 + n, side=100.0)
+    ants = 150_000
+    col = orc.Colony(d, ants=ants, cand_len=cl, alpha=1, beta=2, seed=9)
+    rng = np.random.default_rng(n)
+    tau = rng.uniform(0.2, 1.0, size=(n, n)).astype(np.float32)
+    col.set_pheromone(tau)
+    col.prepare_choice()
+    col.construct(3, nthreads=4)
+    tours = col.tours()
+    keys, cnt = np.unique(tours, axis=0, return_counts=True)
+    counts = {tuple(int(x) for x in k): int(c) for k, c in zip(keys, cnt)}
+    chi2_ok(counts, exact_tour_probs(d, tau, cl, 1, 2), ants)

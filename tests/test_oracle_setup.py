@@ -1,0 +1,93 @@
+"""Pins of the set-up steps of Alg. 1: eta = 1/d (Sec. 2), candidate lists
+(Sec. 4.3), the nearest-neighbour tour and the trail limits of Stuetzle and
+Hoos with p_best (Sec. 5)."""
+import numpy as np
+import pytest
+
+from paper_2003_11902_amd import instances as I
+
+
+def test_heuristic_is_inverse_distance_power(orc):
+    _, d = I.make_instance("clustered", 60, seed=8, clusters=4, sigma=50.0)
+    for beta in (0, 1, 2, 3):
+        col = orc.Colony(d, ants=1, cand_len=8, beta=beta)
+        h = col.heuristic().astype(np.float64)
+        off = ~np.eye(60, dtype=bool)
+        ref = (1.0 / d[off].astype(np.float64)) ** beta
+        rel = np.abs(h[off] - ref) / ref
+        # 1/d rounds once and the beta power multiplies that error by beta;
+        # each of the beta - 1 products rounds once more
+        assert rel.max() <= max(2 * beta - 1, 0) * 2.0 ** -24 * 1.01
+        assert np.all(np.diag(h) == 0)
+
+
+def test_nn_tour_is_greedy(orc):
+    _, d = I.make_instance("uniform", 150, seed=9)
+    t, length = orc.nn_tour(d)
+    t = t.astype(np.int64)
+    assert t[0] == 0 and np.array_equal(np.sort(t), np.arange(150))
+    vis = {0}
+    for k in range(1, 150):
+        cur = t[k - 1]
+        free = [j for j in range(150) if j not in vis]
+        dmin = min(d[cur, j] for j in free)
+        assert d[cur, t[k]] == dmin
+        assert t[k] == min(j for j in free if d[cur, j] == dmin)
+        vis.add(int(t[k]))
+    assert length == int(d[t, np.roll(t, -1)].sum())
+
+
+@pytest.mark.parametrize("n,C,rho", [(198, 15000, 0.02), (1002, 250000, 0.02), (3795, 1200000, 0.5),
+                                     (18512, 100_000_000, 0.3), (6, 40, 0.1)])
+def test_limits_closed_form(orc, n, C, rho):
+    """tau_max = 1/(rho C); tau_min is set so that, once converged, an ant picks
+    the tau_max edge among n/2 choices with probability p_dec and builds the
+    best tour with probability p_dec^n = p_best."""
+    p_best = 0.01
+    pdec = orc.pdec_of(p_best, n)
+    tmin, tmax = orc.limits(rho, C, n, pdec)
+    r32 = np.float32(rho)
+    assert abs(float(tmax) * float(r32) * C - 1.0) < 2e-7
+    ratio = float(tmax) / (float(tmax) + (n / 2 - 1) * float(tmin))
+    assert abs(ratio ** n / p_best - 1.0) < n * 4e-7 + 1e-6
+    assert 0 < tmin < tmax
+
+
+@pytest.mark.parametrize("n", [3, 4, 5])
+def test_limits_collapse_for_tiny_n(orc, n):
+    """For n <= 5 the formula gives tau_min > tau_max; tau_min is then tau_max."""
+    pdec = orc.pdec_of(0.01, n)
+    tmin, tmax = orc.limits(0.02, 10 * n, n, pdec)
+    assert tmin == tmax
+
+
+def test_initial_state(orc):
+    _, d = I.make_instance("uniform", 80, seed=10)
+    col = orc.Colony(d, ants=4, cand_len=10, rho=0.1)
+    _, cnn = col.nn_tour()
+    tmin, tmax = col.limits()
+    e_tmin, e_tmax = orc.limits(0.1, cnn, 80, col.pdec)
+    assert (tmin, tmax) == (e_tmin, e_tmax)
+    assert np.all(col.pheromone() == tmax)
+    assert col.best()[1] == -1
+
+
+def test_candidate_list_longer_than_n(orc):
+    _, d = I.make_instance("uniform", 10, seed=11)
+    col = orc.Colony(d, ants=64, cand_len=32)
+    assert col.cl == 9
+    col.prepare_choice()
+    col.construct(0)
+    s, _ = col.fallback()
+    assert s.sum() == 0
+
+
+def test_invalid_arguments_rejected(orc):
+    _, d = I.make_instance("uniform", 10, seed=11)
+    for kw in (dict(ants=0), dict(rho=0.0), dict(rho=1.0), dict(cand_len=-1), dict(ls_nn=10)):
+        args = dict(ants=4, cand_len=4)
+        args.update(kw)
+        with pytest.raises(ValueError):
+            orc.Colony(d, **args)
+    with pytest.raises(ValueError):
+        orc.Colony(d[:2, :2], ants=1)
