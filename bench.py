@@ -1,0 +1,154 @@
+"""Throughput of the MMAS hot path on one MI355X.
+
+One step is one iteration of Alg. 1 on the n = 1002 clustered workload
+(1002 ants, candidate lists of 32, alpha 1, beta 2, rho 0.02): choice_info
+(folded into the previous update), tour construction for every ant, iteration
+and global best with the trail limits, evaporation + deposit + clamp. The
+metric is tours constructed per second; inputs are resident in HBM before the
+timed region starts.
+
+Prints one JSON line with, besides the contract fields, the roofline of the
+construction kernel (algorithmic bytes per launch / its average duration,
+measured with HIP events on the library's stream) and the CPU oracle timed on
+a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def algorithmic_bytes(n: int, cl: int, ants: int, fallback_nodes: float) -> float:
+    """Bytes one construction launch must move: per step the candidate row
+    (cl ids of 2 B and cl choice_info values of 4 B), per tour the tour itself
+    (2 B per city) and its edge lengths (4 B per city), and 4 B of
+    choice_info per city enumerated in the all-node fallback."""
+    per_tour = (n - 1) * cl * 6 + 2 * n + 4 * n
+    return ants * per_tour + 4.0 * fallback_nodes
+
+
+def cpu_baseline(dist, w, seed, budget_s):
+    from oracle import oracle as O
+
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = max(1, min(threads, 16))
+    o = O.Colony(dist, w["ants"], cand_len=w["cand_len"], alpha=w["alpha"], beta=w["beta"],
+                 rho=w["rho"], seed=seed)
+    t0 = time.perf_counter()
+    it = 0
+    while True:
+        o.iterate(it, threads)
+        it += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or it >= 200:
+            break
+    return {"value": w["ants"] * it / el, "unit": "tours/s", "cores": threads, "kind": "oracle",
+            "sample": f"{it} full iterations (choice, construction of {w['ants']} tours, update) of the same "
+                      f"workload, OpenMP over ants, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="clustered1002")
+    ap.add_argument("--tabu", default="bitmask", choices=["bitmask", "compact"])
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method's "
+              "multi-GPU sharding is not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2003_11902_amd import instances as I
+    from paper_2003_11902_amd import mmas as M
+
+    torch.cuda.set_device(0)
+    xy, dist, w = I.workload_instance(args.workload)
+    n = w["n"]
+    col = M.Colony(dist, w["ants"], cand_len=w["cand_len"], alpha=w["alpha"], beta=w["beta"],
+                   rho=w["rho"], seed=args.seed, tabu=args.tabu, pher=w["pher"], ls_nn=w["ls_nn"])
+    stream = col.stream
+
+    def step(it):
+        col.prepare_choice_info()
+        col.construct(it)
+        if w["ls_nn"]:
+            col.two_opt()
+        col.update_pheromone()
+
+    it = 0
+    for _ in range(args.warmup):
+        step(it)
+        it += 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(it)
+        it += 1
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    print(f"[bench] timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+
+    # per-kernel pass: HIP events around the construction launch on its stream
+    kp = min(args.steps, 50)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(kp)]
+    fb_nodes = []
+    for k in range(kp):
+        col.prepare_choice_info()
+        ev[k][0].record(stream)
+        col.construct(it)
+        ev[k][1].record(stream)
+        col.update_pheromone()
+        it += 1
+        fb_nodes.append(int(col.fallback()[1].sum()))
+    torch.cuda.synchronize()
+    cons_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    nbytes = algorithmic_bytes(n, col.cl, w["ants"], float(np.mean(fb_nodes)))
+    achieved = nbytes / (cons_ms * 1e-3) / 1e9
+
+    tours_per_s = w["ants"] * args.steps / elapsed
+    out = {
+        "metric": "tours constructed/sec at n=1002 (1 GPU)",
+        "value": tours_per_s,
+        "unit": "tours/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "ants": w["ants"], "cand_len": w["cand_len"],
+                   "alpha": w["alpha"], "beta": w["beta"], "rho": w["rho"], "tabu": args.tabu,
+                   "pheromone": w["pher"], "instance": f"{w['kind']} seed {w['seed']}"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_construct", "kernel_ms": cons_ms,
+                     "bytes_per_launch": nbytes},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(dist, w, args.seed, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,193 @@
+/*
+ * mmas.h -- C ABI of the MI355X (gfx950) MAX-MIN Ant System hot path.
+ *
+ * The method is the GPU MAX-MIN Ant System of Skinderowicz, "Implementing a
+ * GPU-based parallel MAX-MIN Ant System" (FGCS 2020): every ant builds a TSP
+ * tour (Alg. 1) by repeated node selection with weighted reservoir sampling
+ * (Alg. 4, Sec. 4.2.2) over the candidate list of its current node (Sec. 4.3),
+ * falling back to every unvisited node when the list is exhausted, with its
+ * visited set in a bitmask tabu or the compact tabu (Sec. 4.1); then the
+ * iteration best deposits pheromone after evaporation, within the trail limits
+ * [tau_min, tau_max] (Sec. 3.1).
+ *
+ * Conventions shared by every call:
+ *  - Device memory: the caller owns one device buffer (the workspace, at
+ *    least mmas_workspace_bytes() bytes, 256-byte aligned) and lends it to the
+ *    context from mmas_create until mmas_destroy. The library allocates no
+ *    device memory of its own.
+ *  - Streams: every call enqueues on the hipStream_t given to mmas_create and
+ *    returns without waiting, except where a call says it synchronises.
+ *  - Errors: every call returns a status and never aborts. Kernel faults show
+ *    up as MMAS_EHIP at the next synchronising call.
+ *  - Determinism: one (distance matrix, parameters, seed, iteration) has
+ *    exactly one result. Every random number is drawn from Philox4x32-10
+ *    keyed on (seed, iteration, ant, step, slot); keys are ln(u)/w in FP32
+ *    with IEEE division; equal keys go to the lowest node index. The tabu
+ *    variant and the launch shape never change a result.
+ *  - Threading: a context is not thread-safe; separate contexts are
+ *    independent.
+ */
+#ifndef MMAS_H
+#define MMAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mmas_status {
+    MMAS_OK = 0,
+    MMAS_EINVAL = -1,      /* an argument or the distance matrix is invalid */
+    MMAS_EUNSUPPORTED = -2,/* valid, but outside what this build implements */
+    MMAS_ENOSPACE = -3,    /* workspace smaller than mmas_workspace_bytes() */
+    MMAS_EHIP = -4,        /* a HIP runtime call or a kernel failed */
+    MMAS_ESTATE = -5       /* call out of order (e.g. update before construct) */
+} mmas_status;
+
+enum { MMAS_TABU_BITMASK = 0, MMAS_TABU_COMPACT = 1 };
+enum { MMAS_PHER_DENSE = 0, MMAS_PHER_CANDIDATES = 1 };
+
+/* Run parameters. Sec. 5 lists the paper's settings (m = n ants, alpha = 1,
+ * beta = 2, p_best = 0.01); Sec. 4.3 the candidate lists. */
+typedef struct mmas_params {
+    int32_t n;         /* cities, 3 <= n <= 65535 (node ids fit in 16 bits, Table 1) */
+    int32_t ants;      /* m >= 1 */
+    int32_t cand_len;  /* candidate-list length cl, 0..64; cl >= n-1 means all other
+                          cities (used as n-1); 0 means no list (every step is the
+                          all-node fallback) */
+    int32_t alpha;     /* pheromone exponent, integer 0..8 */
+    int32_t beta;      /* heuristic exponent, integer 0..8 */
+    float rho;         /* evaporation rate in (0,1): tau <- max((1-rho) tau, tau_min) */
+    double p_best;     /* (0,1): probability of rebuilding the best tour once converged */
+    uint64_t seed;     /* Philox key */
+    int32_t tabu;      /* MMAS_TABU_BITMASK or MMAS_TABU_COMPACT */
+    int32_t pher_mode; /* MMAS_PHER_DENSE: n*n trails; MMAS_PHER_CANDIDATES: trails
+                          stored only on the (i, cand[i][r]) edges, every other edge
+                          held at tau_min (needs cand_len >= 1) */
+    int32_t ls_nn;     /* 2-opt neighbour-list length, 0 = no local search */
+    int32_t reserved;  /* must be 0 */
+} mmas_params;
+
+typedef struct mmas_ctx mmas_ctx;
+
+/* Per-context scalars kept in device memory (layout fixed; read it with
+ * mmas_read(MMAS_BUF_STATE)). */
+typedef struct mmas_device_state {
+    float tau_min;     /* current trail limits */
+    float tau_max;
+    float delta;       /* deposit of the last update, 1/C_ib */
+    int32_t ib_ant;    /* iteration-best ant of the last update, -1 before */
+    int64_t ib_len;    /* its length, -1 before */
+    int64_t gb_len;    /* global-best length, -1 while there is none */
+    int64_t nn_len;    /* nearest-neighbour tour length (set-up) */
+    uint32_t flags;    /* 1/2/4: distance matrix asymmetric / non-zero diagonal /
+                          non-positive off the diagonal (set-up); 8: a
+                          construction step found no city (never expected) */
+    uint32_t updates;  /* number of completed updates */
+} mmas_device_state;
+
+/* Views into the workspace, for mmas_buffer and mmas_read. */
+enum {
+    MMAS_BUF_DIST = 0,      /* int32 n*n, row-major */
+    MMAS_BUF_PHEROMONE = 1, /* float n*n (dense) or n*cl (candidates; row i, rank r) */
+    MMAS_BUF_CHOICE = 2,    /* float n*n, tau^alpha * eta^beta (dense only) */
+    MMAS_BUF_CHC = 3,       /* float n*cl, choice_info along the candidate lists */
+    MMAS_BUF_CAND = 4,      /* uint16 n*cl, candidate lists sorted by (d, index) */
+    MMAS_BUF_HEUR = 5,      /* float n*n eta^beta (dense) or n*cl (candidates) */
+    MMAS_BUF_TOURS = 6,     /* uint16 ants*n, tour of ant a at row a */
+    MMAS_BUF_LENGTHS = 7,   /* int64 ants, closing edge included */
+    MMAS_BUF_GB_TOUR = 8,   /* uint16 n */
+    MMAS_BUF_NN_TOUR = 9,   /* uint16 n */
+    MMAS_BUF_FALLBACK = 10, /* int64 2*ants: fallback steps, then nodes enumerated */
+    MMAS_BUF_STATE = 11,    /* mmas_device_state */
+    MMAS_BUF_LSNN = 12,     /* uint16 n*ls_nn, 2-opt neighbour lists */
+    MMAS_BUF_COUNT = 13
+};
+
+/* Bytes the workspace must have for these parameters; 0 if they are invalid. */
+size_t mmas_workspace_bytes(const mmas_params* p);
+
+/* Set-up (Alg. 1 before its loop). Copies `dist_host` (n*n int32, row-major,
+ * host memory; the caller may free it on return) into the workspace, checks it
+ * (symmetric, zero diagonal, positive elsewhere: Sec. 2 requires positive
+ * distances and the deposit of Sec. 3.1 treats (i,j) and (j,i) as one edge),
+ * and then on the GPU: eta = 1/d and eta^beta (Sec. 2), the candidate lists of
+ * the cl nearest cities by (distance, index) (Sec. 4.3), the 2-opt neighbour
+ * lists, the nearest-neighbour tour from city 0 (ties to the lowest index),
+ * the trail limits from its length (tau_max = 1/(rho C), tau_min =
+ * tau_max (1 - p_best^(1/n)) / ((n/2 - 1) p_best^(1/n)) in FP64, rounded to
+ * FP32, tau_min capped at tau_max), and tau <- tau_max.
+ * `dev_ws`/`ws_bytes`: the workspace; `hip_stream`: a hipStream_t (NULL = the
+ * null stream). Synchronises once (to report a bad matrix).
+ * Errors: EINVAL (parameters or matrix), ENOSPACE, EHIP. */
+mmas_status mmas_create(const int32_t* dist_host, const mmas_params* p, void* dev_ws,
+                        size_t ws_bytes, void* hip_stream, mmas_ctx** out);
+
+/* choice_info = tau^alpha * eta^beta in FP32 (Sec. 3.1), dense and along the
+ * candidate lists. The pheromone update refreshes it as it writes tau, so this
+ * launches only when tau changed in another way (set-up, mmas_set_pheromone). */
+mmas_status mmas_prepare_choice_info(mmas_ctx* ctx);
+
+/* Tour construction for iteration `iteration` (the inner loops of Alg. 1):
+ * every ant starts at a uniformly drawn city and takes n-1 steps; each step
+ * selects, among the unvisited cities of the current city's candidate list,
+ * the one with the largest key ln(u)/choice_info (Alg. 4 with logarithmic
+ * keys, Sec. 4.2.2), or, when none is left, among all unvisited cities with
+ * the same rule. Writes MMAS_BUF_TOURS, MMAS_BUF_LENGTHS, MMAS_BUF_FALLBACK. */
+mmas_status mmas_construct(mmas_ctx* ctx, uint32_t iteration);
+
+/* 2-opt on every ant's tour with ls_nn-nearest-neighbour lists and don't-look
+ * bits (Sec. 5.5), as a sequential first-improvement search (cities in index
+ * order, successor direction before predecessor, neighbours by rank while the
+ * first partial gain is positive; the shorter path is reversed). Updates
+ * tours and lengths. EUNSUPPORTED if ls_nn == 0; ESTATE before a construct. */
+mmas_status mmas_two_opt(mmas_ctx* ctx);
+
+/* The end of an iteration of Alg. 1: the iteration best (shortest tour,
+ * lowest ant on ties); if it beats the global best (or there is none) it
+ * becomes the global best and the limits are recomputed from its length;
+ * then tau <- max(fl((1-rho) tau), tau_min), plus 1/C_ib on both directions
+ * of the iteration best's edges, then min(., tau_max) on every stored trail;
+ * choice_info is refreshed in the same pass. ESTATE before a construct. */
+mmas_status mmas_update_pheromone(mmas_ctx* ctx);
+
+/* Global best so far. Synchronises. `tour_host` (n int32) may be NULL.
+ * *len_host = -1 while there is no global best. */
+mmas_status mmas_best(mmas_ctx* ctx, int32_t* tour_host, int64_t* len_host);
+
+/* Device address and size of a workspace view (MMAS_BUF_*). No copy. */
+mmas_status mmas_buffer(mmas_ctx* ctx, int which, void** dev_ptr, size_t* bytes);
+
+/* Copies a view to host memory (`bytes` must equal the view's size).
+ * Synchronises. */
+mmas_status mmas_read(mmas_ctx* ctx, int which, void* host_dst, size_t bytes);
+
+/* Replaces the stored trails (n*n or n*cl floats, host memory; finite,
+ * positive). Synchronises. Marks choice_info stale. */
+mmas_status mmas_set_pheromone(mmas_ctx* ctx, const float* host_src);
+
+/* Waits for all work the context has enqueued. */
+mmas_status mmas_synchronize(mmas_ctx* ctx);
+
+/* Frees the context (not the workspace). NULL is a no-op. */
+void mmas_destroy(mmas_ctx* ctx);
+
+/* Diagnostics, for checking the device arithmetic against an independent
+ * implementation: the device FP32 logarithm of `count` values in (0,1)
+ * (`dev_u` -> `dev_out`, device arrays), and the Philox draw words for
+ * (seed, it[i], ant[i], step[i], slot[i]) (device arrays of `count`). Both
+ * enqueue on `hip_stream` and return without waiting. */
+mmas_status mmas_eval_log(const float* dev_u, float* dev_out, size_t count, void* hip_stream);
+mmas_status mmas_eval_draws(uint64_t seed, const uint32_t* dev_it, const uint32_t* dev_ant,
+                            const uint32_t* dev_step, const uint32_t* dev_slot, uint32_t* dev_out,
+                            size_t count, void* hip_stream);
+
+/* Static text for a status. */
+const char* mmas_status_str(mmas_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,194 @@
+// Device-side building blocks shared by the kernels of the library:
+// counter-based random numbers, the FP32 logarithm used for the reservoir
+// keys, the orderable (key, node) encoding and wave64 reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mmas {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror and Shaw, SC'11): per round, words 0 and
+// 2 are multiplied by two fixed constants; the new counter is
+// (hi(M1*c2) ^ c1 ^ k0, lo(M1*c2), hi(M0*c0) ^ c3 ^ k1, lo(M0*c0)); the key is
+// bumped by the two Weyl constants after each round.
+// ---------------------------------------------------------------------------
+struct Words4 {
+    uint32_t w[4];
+};
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Words4{{c0, c1, c2, c3}};
+}
+
+// The Philox block that holds draw `slot` of (iteration, ant, step): counter
+// ((slot >> 2) | (step << 16), ant, iteration, 0), key = the 64-bit seed.
+// The draw is word (slot & 3) of the block.
+__device__ __forceinline__ Words4 draw_block(uint64_t seed, uint32_t it, uint32_t ant, uint32_t step,
+                                             uint32_t slot) {
+    return philox4x32_10((slot >> 2) | (step << 16), ant, it, 0u, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+__device__ __forceinline__ uint32_t pick_word(const Words4& b, uint32_t idx) {
+    // idx in 0..3; masks instead of an indexed array so the words stay in
+    // registers
+    const uint32_t m0 = 0u - (uint32_t)(idx == 0u), m1 = 0u - (uint32_t)(idx == 1u);
+    const uint32_t m2 = 0u - (uint32_t)(idx == 2u), m3 = 0u - (uint32_t)(idx == 3u);
+    return (b.w[0] & m0) | (b.w[1] & m1) | (b.w[2] & m2) | (b.w[3] & m3);
+}
+
+// u = (2 * (x >> 9) + 1) * 2^-24: exact, strictly inside (0, 1).
+__device__ __forceinline__ float u01(uint32_t x) {
+    return (float)(2u * (x >> 9) + 1u) * 0x1p-24f;
+}
+
+// Natural logarithm of u in (0, 1) in FP32 (every operation rounded on its own;
+// the build disables contraction). u = m 2^e with m in (sqrt(2)/2, sqrt(2)];
+// f = m - 1, s = f/(2+f) so that (1+s)/(1-s) = 1+f; ln(1+f) = 2 atanh(s)
+// = 2s + s R with R = z(2/3 + z(2/5 + z(2/7 + z(2/9 + z 2/11)))), z = s^2;
+// as 2s = f - s f and s f = h - s h for h = f^2/2, ln(1+f) = f - (h - s(h+R)).
+// ln 2 is split in a 15-bit head (e * head is exact) and a rounded tail.
+__device__ __forceinline__ float log_u01(float u) {
+    const float kLn2Hi = __uint_as_float(0x3F317200u);
+    const float kLn2Lo = __uint_as_float(0x35BFBE8Eu);
+    const float kSqrt2 = __uint_as_float(0x3FB504F3u);
+    const float c3 = 2.0f / 3.0f, c5 = 2.0f / 5.0f, c7 = 2.0f / 7.0f, c9 = 2.0f / 9.0f,
+                c11 = 2.0f / 11.0f;
+    const uint32_t b = __float_as_uint(u);
+    int e = (int)(b >> 23) - 127;
+    float m = __uint_as_float((b & 0x007FFFFFu) | 0x3F800000u);
+    if (m > kSqrt2) {
+        m = m * 0.5f;
+        e = e + 1;
+    }
+    const float f = m - 1.0f;
+    const float s = f / (2.0f + f);
+    const float z = s * s;
+    const float R = z * (c3 + z * (c5 + z * (c7 + z * (c9 + z * c11))));
+    const float h = 0.5f * f * f;
+    const float ef = (float)e;
+    const float hi = ef * kLn2Hi;
+    const float lo = ef * kLn2Lo;
+    return hi + (f - (h - (s * (h + R) + lo)));
+}
+
+// x^k by left-to-right multiplication, x^0 = 1.
+__device__ __forceinline__ float powi(float x, int k) {
+    float r = 1.0f;
+    for (int i = 0; i < k; ++i) r = r * x;
+    return r;
+}
+
+// eta^beta with eta = 1/d.
+__device__ __forceinline__ float heur_from_dist(int32_t d, int beta) {
+    return powi(1.0f / (float)d, beta);
+}
+
+// Order-preserving map of a non-NaN float to uint32 (larger float -> larger
+// code); every non-NaN float maps above 0, so 0 means "no key".
+__device__ __forceinline__ uint32_t ord_key(float k) {
+    const uint32_t b = __float_as_uint(k);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// ---------------------------------------------------------------------------
+// wave64 reductions. Rows of 16 lanes reduce through DPP lane permutations
+// (quad swaps, half-row and row mirrors); the four row results are read into
+// scalar registers and combined there. Every lane must be active.
+// ---------------------------------------------------------------------------
+template <int kCtrl>
+__device__ __forceinline__ uint32_t dpp(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kCtrl, 0xF, 0xF, false);
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+    x = max(x, dpp<0xB1>(x));   // quad_perm [1,0,3,2]
+    x = max(x, dpp<0x4E>(x));   // quad_perm [2,3,0,1]
+    x = max(x, dpp<0x141>(x));  // row_half_mirror
+    x = max(x, dpp<0x140>(x));  // row_mirror
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 0);
+    const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)x, 16);
+    const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)x, 32);
+    const uint32_t r3 = (uint32_t)__builtin_amdgcn_readlane((int)x, 48);
+    return max(max(r0, r1), max(r2, r3));
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+    x = min(x, dpp<0xB1>(x));
+    x = min(x, dpp<0x4E>(x));
+    x = min(x, dpp<0x141>(x));
+    x = min(x, dpp<0x140>(x));
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 0);
+    const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)x, 16);
+    const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)x, 32);
+    const uint32_t r3 = (uint32_t)__builtin_amdgcn_readlane((int)x, 48);
+    return min(min(r0, r1), min(r2, r3));
+}
+
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t x) {
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
+    return x;
+}
+
+// Argmax of (key code, -node) over the wave: the node with the largest key,
+// the lowest node among equal keys. `code` is 0 for lanes without a key.
+// Returns the node, or 0xFFFFFFFF if no lane had a key.
+__device__ __forceinline__ uint32_t wave_select(uint32_t code, uint32_t node) {
+    const uint32_t best = wave_max_u32(code);
+    if (best == 0u) return 0xFFFFFFFFu;
+    const uint64_t tied = __ballot(code == best);
+    if (__popcll(tied) == 1) {
+        const int lane = __ffsll((unsigned long long)tied) - 1;
+        return (uint32_t)__builtin_amdgcn_readlane((int)node, lane);
+    }
+    return wave_min_u32(code == best ? node : 0xFFFFFFFFu);
+}
+
+}  // namespace mmas
+
+namespace mmas {
+
+// Trail limits (Stuetzle and Hoos, with p_best): tau_max = 1/(rho C),
+// tau_min = tau_max (1 - pdec) / ((n/2 - 1) pdec) with pdec = p_best^(1/n),
+// in FP64 then rounded to FP32; tau_min never exceeds tau_max.
+__device__ __forceinline__ void trail_limits(float rho, int64_t C, int n, double pdec, float* tmin,
+                                             float* tmax) {
+    const double hi = 1.0 / ((double)rho * (double)C);
+    const double lo = (hi * (1.0 - pdec)) / (((double)n / 2.0 - 1.0) * pdec);
+    const float fh = (float)hi;
+    float fl = (float)lo;
+    if (fl > fh) fl = fh;
+    *tmin = fl;
+    *tmax = fh;
+}
+
+// Lexicographic min of (value, index) packed as value << 32 | index for
+// non-negative 31-bit values.
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
+    for (int o = 32; o >= 1; o >>= 1) {
+        const uint64_t y = __shfl_xor(x, o);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+}  // namespace mmas

@@ -1,0 +1,65 @@
+// Host-side declarations shared by the translation units of libmmas: the
+// workspace views of one context and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/mmas.h"
+
+namespace mmas {
+
+// Device views of one context's workspace (all inside the caller's buffer).
+struct Views {
+    int32_t* dist;      // n*n
+    float* heur;        // n*n (dense) or n*cl (candidates): eta^beta
+    float* tau;         // n*n (dense) or n*cl (candidates)
+    float* choice;      // n*n (dense) or nullptr
+    float* chc;         // n*cl
+    uint16_t* cand;     // n*cl
+    uint16_t* lsnn;     // n*ls_nn or nullptr
+    uint16_t* tours;    // ants*n
+    int64_t* lengths;   // ants
+    int64_t* fallback;  // 2*ants
+    uint16_t* gb_tour;  // n
+    uint16_t* nn_tour;  // n
+    uint16_t* succ;     // n: successor of each city in the iteration best
+    uint16_t* pred;     // n
+    mmas_device_state* state;
+};
+
+// Problem constants every kernel needs.
+struct Shape {
+    int n;
+    int ants;
+    int cl;      // effective candidate-list length, min(cand_len, n-1)
+    int alpha;
+    int beta;
+    int ls_nn;
+    int pher;    // MMAS_PHER_*
+    int tabu;    // MMAS_TABU_*
+    float rho;
+    double pdec; // p_best^(1/n)
+    uint64_t seed;
+};
+
+// ---- set-up (prep.hip) ----
+hipError_t launch_validate(const Views& v, const Shape& s, hipStream_t st);
+hipError_t launch_heuristic(const Views& v, const Shape& s, hipStream_t st);
+hipError_t launch_nearest(const int32_t* dist, int n, int k, uint16_t* out, hipStream_t st);
+hipError_t launch_nn_tour(const Views& v, const Shape& s, hipStream_t st);
+hipError_t launch_init_trails(const Views& v, const Shape& s, hipStream_t st);
+
+// ---- per iteration ----
+hipError_t launch_choice(const Views& v, const Shape& s, hipStream_t st);             // update.hip
+hipError_t launch_construct(const Views& v, const Shape& s, uint32_t it, hipStream_t st); // construct.hip
+hipError_t launch_two_opt(const Views& v, const Shape& s, hipStream_t st);           // two_opt.hip
+hipError_t launch_update(const Views& v, const Shape& s, hipStream_t st);            // update.hip
+
+// LDS bytes one ant needs in the construction kernel (0 if it cannot run).
+size_t construct_lds_per_ant(const Shape& s);
+// LDS bytes of the 2-opt kernel (one tour per workgroup).
+size_t two_opt_lds_bytes(const Shape& s);
+
+}  // namespace mmas

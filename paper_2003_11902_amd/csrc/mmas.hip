@@ -1,0 +1,289 @@
+// C ABI of libmmas: parameter checks, the workspace layout, and the call
+// sequence of Alg. 1 on one HIP stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+using mmas::Shape;
+using mmas::Views;
+
+struct mmas_ctx {
+    mmas_params p;
+    Shape s;
+    Views v;
+    hipStream_t stream;
+    char* ws;
+    size_t ws_bytes;
+    size_t off[MMAS_BUF_COUNT];
+    size_t len[MMAS_BUF_COUNT];
+    size_t off_succ, off_pred;
+    bool choice_stale;
+    bool constructed;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+bool params_ok(const mmas_params* p) {
+    if (!p) return false;
+    if (p->n < 3 || p->n > 65535) return false;
+    if (p->ants < 1) return false;
+    if (p->cand_len < 0 || p->cand_len > 64) return false;
+    if (p->alpha < 0 || p->alpha > 8 || p->beta < 0 || p->beta > 8) return false;
+    if (!(p->rho > 0.0f && p->rho < 1.0f)) return false;
+    if (!(p->p_best > 0.0 && p->p_best < 1.0)) return false;
+    if (p->tabu != MMAS_TABU_BITMASK && p->tabu != MMAS_TABU_COMPACT) return false;
+    if (p->pher_mode != MMAS_PHER_DENSE && p->pher_mode != MMAS_PHER_CANDIDATES) return false;
+    const int cl = p->cand_len < p->n - 1 ? p->cand_len : p->n - 1;
+    if (p->pher_mode == MMAS_PHER_CANDIDATES && cl == 0) return false;
+    if (p->ls_nn < 0 || p->ls_nn > 64 || p->ls_nn > p->n - 1) return false;
+    if (p->reserved != 0) return false;
+    return true;
+}
+
+Shape shape_of(const mmas_params* p) {
+    Shape s{};
+    s.n = p->n;
+    s.ants = p->ants;
+    s.cl = p->cand_len < p->n - 1 ? p->cand_len : p->n - 1;
+    s.alpha = p->alpha;
+    s.beta = p->beta;
+    s.ls_nn = p->ls_nn;
+    s.pher = p->pher_mode;
+    s.tabu = p->tabu;
+    s.rho = p->rho;
+    s.pdec = std::pow(p->p_best, 1.0 / (double)p->n);
+    s.seed = p->seed;
+    return s;
+}
+
+// Byte sizes of every view, then their offsets (256-byte aligned).
+size_t layout(const Shape& s, size_t* off, size_t* len, size_t* off_succ, size_t* off_pred) {
+    const size_t n = (size_t)s.n, cl = (size_t)s.cl, ants = (size_t)s.ants;
+    const bool dense = s.pher == MMAS_PHER_DENSE;
+    len[MMAS_BUF_DIST] = 4 * n * n;
+    len[MMAS_BUF_PHEROMONE] = dense ? 4 * n * n : 4 * n * cl;
+    len[MMAS_BUF_CHOICE] = dense ? 4 * n * n : 0;
+    len[MMAS_BUF_CHC] = 4 * n * cl;
+    len[MMAS_BUF_CAND] = 2 * n * cl;
+    len[MMAS_BUF_HEUR] = dense ? 4 * n * n : 4 * n * cl;
+    len[MMAS_BUF_TOURS] = 2 * n * ants;
+    len[MMAS_BUF_LENGTHS] = 8 * ants;
+    len[MMAS_BUF_GB_TOUR] = 2 * n;
+    len[MMAS_BUF_NN_TOUR] = 2 * n;
+    len[MMAS_BUF_FALLBACK] = 16 * ants;
+    len[MMAS_BUF_STATE] = sizeof(mmas_device_state);
+    len[MMAS_BUF_LSNN] = 2 * n * (size_t)s.ls_nn;
+    size_t pos = 0;
+    for (int b = 0; b < MMAS_BUF_COUNT; ++b) {
+        off[b] = pos;
+        pos = align_up(pos + len[b]);
+    }
+    *off_succ = pos;
+    pos = align_up(pos + 2 * n);
+    *off_pred = pos;
+    pos = align_up(pos + 2 * n);
+    return pos;
+}
+
+template <class T>
+T* at(char* base, size_t off, size_t len) {
+    return len ? reinterpret_cast<T*>(base + off) : nullptr;
+}
+
+mmas_status hip_status(hipError_t e) { return e == hipSuccess ? MMAS_OK : MMAS_EHIP; }
+
+}  // namespace
+
+extern "C" {
+
+size_t mmas_workspace_bytes(const mmas_params* p) {
+    if (!params_ok(p)) return 0;
+    Shape s = shape_of(p);
+    size_t off[MMAS_BUF_COUNT], len[MMAS_BUF_COUNT], os, op;
+    return layout(s, off, len, &os, &op);
+}
+
+mmas_status mmas_create(const int32_t* dist_host, const mmas_params* p, void* dev_ws, size_t ws_bytes,
+                        void* hip_stream, mmas_ctx** out) {
+    if (!out) return MMAS_EINVAL;
+    *out = nullptr;
+    if (!dist_host || !params_ok(p) || !dev_ws) return MMAS_EINVAL;
+    if (reinterpret_cast<uintptr_t>(dev_ws) % kAlign) return MMAS_EINVAL;
+    Shape s = shape_of(p);
+    mmas_ctx* c = new (std::nothrow) mmas_ctx();
+    if (!c) return MMAS_EHIP;
+    c->p = *p;
+    c->s = s;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->ws = reinterpret_cast<char*>(dev_ws);
+    c->ws_bytes = ws_bytes;
+    const size_t need = layout(s, c->off, c->len, &c->off_succ, &c->off_pred);
+    if (ws_bytes < need) {
+        delete c;
+        return MMAS_ENOSPACE;
+    }
+    if (s.tabu == MMAS_TABU_COMPACT || s.tabu == MMAS_TABU_BITMASK) {
+        int dev = 0, maxlds = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+            delete c;
+            return MMAS_EHIP;
+        }
+        if (mmas::construct_lds_per_ant(s) > (size_t)maxlds) {
+            delete c;
+            return MMAS_EUNSUPPORTED;
+        }
+    }
+    Views& v = c->v;
+    char* b = c->ws;
+    v.dist = at<int32_t>(b, c->off[MMAS_BUF_DIST], c->len[MMAS_BUF_DIST]);
+    v.tau = at<float>(b, c->off[MMAS_BUF_PHEROMONE], c->len[MMAS_BUF_PHEROMONE]);
+    v.choice = at<float>(b, c->off[MMAS_BUF_CHOICE], c->len[MMAS_BUF_CHOICE]);
+    v.chc = at<float>(b, c->off[MMAS_BUF_CHC], c->len[MMAS_BUF_CHC]);
+    v.cand = at<uint16_t>(b, c->off[MMAS_BUF_CAND], c->len[MMAS_BUF_CAND]);
+    v.heur = at<float>(b, c->off[MMAS_BUF_HEUR], c->len[MMAS_BUF_HEUR]);
+    v.tours = at<uint16_t>(b, c->off[MMAS_BUF_TOURS], c->len[MMAS_BUF_TOURS]);
+    v.lengths = at<int64_t>(b, c->off[MMAS_BUF_LENGTHS], c->len[MMAS_BUF_LENGTHS]);
+    v.gb_tour = at<uint16_t>(b, c->off[MMAS_BUF_GB_TOUR], c->len[MMAS_BUF_GB_TOUR]);
+    v.nn_tour = at<uint16_t>(b, c->off[MMAS_BUF_NN_TOUR], c->len[MMAS_BUF_NN_TOUR]);
+    v.fallback = at<int64_t>(b, c->off[MMAS_BUF_FALLBACK], c->len[MMAS_BUF_FALLBACK]);
+    v.state = at<mmas_device_state>(b, c->off[MMAS_BUF_STATE], c->len[MMAS_BUF_STATE]);
+    v.lsnn = at<uint16_t>(b, c->off[MMAS_BUF_LSNN], c->len[MMAS_BUF_LSNN]);
+    v.succ = reinterpret_cast<uint16_t*>(b + c->off_succ);
+    v.pred = reinterpret_cast<uint16_t*>(b + c->off_pred);
+
+    hipStream_t st = c->stream;
+    hipError_t e = hipMemcpyAsync(v.dist, dist_host, c->len[MMAS_BUF_DIST], hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(v.state, 0, sizeof(mmas_device_state), st);
+    if (e == hipSuccess) e = mmas::launch_validate(v, s, st);
+    if (e == hipSuccess) e = mmas::launch_nearest(v.dist, s.n, s.cl, v.cand, st);
+    if (e == hipSuccess) e = mmas::launch_nearest(v.dist, s.n, s.ls_nn, v.lsnn, st);
+    if (e == hipSuccess) e = mmas::launch_heuristic(v, s, st);
+    if (e == hipSuccess) e = mmas::launch_nn_tour(v, s, st);
+    if (e == hipSuccess) e = mmas::launch_init_trails(v, s, st);
+    mmas_device_state hs;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hs, v.state, sizeof(hs), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        delete c;
+        return MMAS_EHIP;
+    }
+    if (hs.flags != 0u || !std::isfinite(hs.tau_max) || !(hs.tau_min > 0.0f)) {
+        delete c;
+        return MMAS_EINVAL;
+    }
+    c->choice_stale = true;
+    c->constructed = false;
+    *out = c;
+    return MMAS_OK;
+}
+
+mmas_status mmas_prepare_choice_info(mmas_ctx* c) {
+    if (!c) return MMAS_EINVAL;
+    if (!c->choice_stale) return MMAS_OK;
+    hipError_t e = mmas::launch_choice(c->v, c->s, c->stream);
+    if (e != hipSuccess) return MMAS_EHIP;
+    c->choice_stale = false;
+    return MMAS_OK;
+}
+
+mmas_status mmas_construct(mmas_ctx* c, uint32_t iteration) {
+    if (!c) return MMAS_EINVAL;
+    mmas_status r = mmas_prepare_choice_info(c);
+    if (r != MMAS_OK) return r;
+    hipError_t e = mmas::launch_construct(c->v, c->s, iteration, c->stream);
+    if (e != hipSuccess) return MMAS_EHIP;
+    c->constructed = true;
+    return MMAS_OK;
+}
+
+mmas_status mmas_two_opt(mmas_ctx* c) {
+    if (!c) return MMAS_EINVAL;
+    if (c->s.ls_nn <= 0) return MMAS_EUNSUPPORTED;
+    if (!c->constructed) return MMAS_ESTATE;
+    hipError_t e = mmas::launch_two_opt(c->v, c->s, c->stream);
+    if (e == hipErrorNotSupported) return MMAS_EUNSUPPORTED;
+    return hip_status(e);
+}
+
+mmas_status mmas_update_pheromone(mmas_ctx* c) {
+    if (!c) return MMAS_EINVAL;
+    if (!c->constructed) return MMAS_ESTATE;
+    hipError_t e = mmas::launch_update(c->v, c->s, c->stream);
+    if (e != hipSuccess) return MMAS_EHIP;
+    c->choice_stale = false;  // refreshed by the fused pass
+    return MMAS_OK;
+}
+
+mmas_status mmas_best(mmas_ctx* c, int32_t* tour_host, int64_t* len_host) {
+    if (!c || !len_host) return MMAS_EINVAL;
+    mmas_device_state hs;
+    std::vector<uint16_t> t(tour_host ? (size_t)c->s.n : 0);
+    hipError_t e = hipMemcpyAsync(&hs, c->v.state, sizeof(hs), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && tour_host)
+        e = hipMemcpyAsync(t.data(), c->v.gb_tour, 2 * (size_t)c->s.n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return MMAS_EHIP;
+    *len_host = hs.gb_len;
+    if (tour_host)
+        for (int k = 0; k < c->s.n; ++k) tour_host[k] = hs.gb_len >= 0 ? (int32_t)t[k] : -1;
+    return MMAS_OK;
+}
+
+mmas_status mmas_buffer(mmas_ctx* c, int which, void** dev_ptr, size_t* bytes) {
+    if (!c || which < 0 || which >= MMAS_BUF_COUNT) return MMAS_EINVAL;
+    if (dev_ptr) *dev_ptr = c->len[which] ? c->ws + c->off[which] : nullptr;
+    if (bytes) *bytes = c->len[which];
+    return MMAS_OK;
+}
+
+mmas_status mmas_read(mmas_ctx* c, int which, void* host_dst, size_t bytes) {
+    if (!c || which < 0 || which >= MMAS_BUF_COUNT || !host_dst) return MMAS_EINVAL;
+    if (bytes != c->len[which]) return MMAS_EINVAL;
+    if (bytes == 0) return MMAS_OK;
+    hipError_t e = hipMemcpyAsync(host_dst, c->ws + c->off[which], bytes, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return hip_status(e);
+}
+
+mmas_status mmas_set_pheromone(mmas_ctx* c, const float* host_src) {
+    if (!c || !host_src) return MMAS_EINVAL;
+    const size_t count = c->len[MMAS_BUF_PHEROMONE] / sizeof(float);
+    for (size_t e = 0; e < count; ++e)
+        if (!std::isfinite(host_src[e]) || host_src[e] < 0.0f) return MMAS_EINVAL;
+    hipError_t e = hipMemcpyAsync(c->v.tau, host_src, c->len[MMAS_BUF_PHEROMONE], hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return MMAS_EHIP;
+    c->choice_stale = true;
+    return MMAS_OK;
+}
+
+mmas_status mmas_synchronize(mmas_ctx* c) {
+    if (!c) return MMAS_EINVAL;
+    return hip_status(hipStreamSynchronize(c->stream));
+}
+
+void mmas_destroy(mmas_ctx* c) { delete c; }
+
+const char* mmas_status_str(mmas_status s) {
+    switch (s) {
+        case MMAS_OK: return "ok";
+        case MMAS_EINVAL: return "invalid argument";
+        case MMAS_EUNSUPPORTED: return "unsupported";
+        case MMAS_ENOSPACE: return "workspace too small";
+        case MMAS_EHIP: return "HIP error";
+        case MMAS_ESTATE: return "call out of order";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

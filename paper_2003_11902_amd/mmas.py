@@ -1,0 +1,298 @@
+"""Python binding of libmmas (include/mmas.h): argument marshalling only.
+
+Every step of the method runs in the HIP library. PyTorch provides the device
+workspace and the stream; nothing here computes any part of the method. If the
+library is not built, importing this module raises ImportError.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmmas.so")
+
+# ---- constants mirrored from include/mmas.h --------------------------------
+MMAS_OK = 0
+MMAS_EINVAL = -1
+MMAS_EUNSUPPORTED = -2
+MMAS_ENOSPACE = -3
+MMAS_EHIP = -4
+MMAS_ESTATE = -5
+
+MMAS_TABU_BITMASK = 0
+MMAS_TABU_COMPACT = 1
+MMAS_PHER_DENSE = 0
+MMAS_PHER_CANDIDATES = 1
+
+MMAS_BUF_DIST = 0
+MMAS_BUF_PHEROMONE = 1
+MMAS_BUF_CHOICE = 2
+MMAS_BUF_CHC = 3
+MMAS_BUF_CAND = 4
+MMAS_BUF_HEUR = 5
+MMAS_BUF_TOURS = 6
+MMAS_BUF_LENGTHS = 7
+MMAS_BUF_GB_TOUR = 8
+MMAS_BUF_NN_TOUR = 9
+MMAS_BUF_FALLBACK = 10
+MMAS_BUF_STATE = 11
+MMAS_BUF_LSNN = 12
+
+TABU = {"bitmask": MMAS_TABU_BITMASK, "compact": MMAS_TABU_COMPACT}
+PHER = {"dense": MMAS_PHER_DENSE, "candidates": MMAS_PHER_CANDIDATES}
+
+EXPORTED = (
+    "mmas_workspace_bytes", "mmas_create", "mmas_prepare_choice_info", "mmas_construct",
+    "mmas_two_opt", "mmas_update_pheromone", "mmas_best", "mmas_buffer", "mmas_read",
+    "mmas_set_pheromone", "mmas_synchronize", "mmas_destroy", "mmas_status_str",
+    "mmas_eval_log", "mmas_eval_draws",
+)
+
+
+class mmas_params(C.Structure):
+    _fields_ = [
+        ("n", C.c_int32), ("ants", C.c_int32), ("cand_len", C.c_int32),
+        ("alpha", C.c_int32), ("beta", C.c_int32), ("rho", C.c_float),
+        ("p_best", C.c_double), ("seed", C.c_uint64), ("tabu", C.c_int32),
+        ("pher_mode", C.c_int32), ("ls_nn", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
+class mmas_device_state(C.Structure):
+    _fields_ = [
+        ("tau_min", C.c_float), ("tau_max", C.c_float), ("delta", C.c_float),
+        ("ib_ant", C.c_int32), ("ib_len", C.c_int64), ("gb_len", C.c_int64),
+        ("nn_len", C.c_int64), ("flags", C.c_uint32), ("updates", C.c_uint32),
+    ]
+
+
+class MmasError(RuntimeError):
+    def __init__(self, status: int, call: str):
+        self.status = status
+        super().__init__(f"{call}: {status_str(status)} ({status})")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is not built; build it with paper_2003_11902_amd/build.py "
+            "(or __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    p = C.c_void_p
+    L.mmas_workspace_bytes.argtypes = [C.POINTER(mmas_params)]
+    L.mmas_workspace_bytes.restype = C.c_size_t
+    L.mmas_create.argtypes = [p, C.POINTER(mmas_params), p, C.c_size_t, p, C.POINTER(p)]
+    L.mmas_create.restype = C.c_int
+    for name in ("mmas_prepare_choice_info", "mmas_two_opt", "mmas_update_pheromone", "mmas_synchronize"):
+        getattr(L, name).argtypes = [p]
+        getattr(L, name).restype = C.c_int
+    L.mmas_construct.argtypes = [p, C.c_uint32]
+    L.mmas_construct.restype = C.c_int
+    L.mmas_best.argtypes = [p, p, C.POINTER(C.c_int64)]
+    L.mmas_best.restype = C.c_int
+    L.mmas_buffer.argtypes = [p, C.c_int, C.POINTER(p), C.POINTER(C.c_size_t)]
+    L.mmas_buffer.restype = C.c_int
+    L.mmas_read.argtypes = [p, C.c_int, p, C.c_size_t]
+    L.mmas_read.restype = C.c_int
+    L.mmas_set_pheromone.argtypes = [p, p]
+    L.mmas_set_pheromone.restype = C.c_int
+    L.mmas_destroy.argtypes = [p]
+    L.mmas_destroy.restype = None
+    L.mmas_eval_log.argtypes = [p, p, C.c_size_t, p]
+    L.mmas_eval_log.restype = C.c_int
+    L.mmas_eval_draws.argtypes = [C.c_uint64, p, p, p, p, p, C.c_size_t, p]
+    L.mmas_eval_draws.restype = C.c_int
+    L.mmas_status_str.argtypes = [C.c_int]
+    L.mmas_status_str.restype = C.c_char_p
+    return L
+
+
+lib = _load()
+
+
+def status_str(s: int) -> str:
+    return lib.mmas_status_str(s).decode()
+
+
+def _check(status: int, call: str):
+    if status != MMAS_OK:
+        raise MmasError(status, call)
+
+
+def mmas_eval_log(u):
+    """Device logarithm of a float32 CUDA tensor (new tensor)."""
+    import torch
+
+    out = torch.empty_like(u)
+    _check(lib.mmas_eval_log(C.c_void_p(u.data_ptr()), C.c_void_p(out.data_ptr()), u.numel(),
+                             C.c_void_p(torch.cuda.current_stream().cuda_stream)), "mmas_eval_log")
+    return out
+
+
+def mmas_eval_draws(seed, it, ant, step, slot):
+    """Device Philox draw words for int32/uint32 CUDA tensors of equal length."""
+    import torch
+
+    out = torch.empty_like(it)
+    _check(lib.mmas_eval_draws(seed, *(C.c_void_p(t.data_ptr()) for t in (it, ant, step, slot)),
+                               C.c_void_p(out.data_ptr()), it.numel(),
+                               C.c_void_p(torch.cuda.current_stream().cuda_stream)), "mmas_eval_draws")
+    return out
+
+
+def make_params(n, ants, cand_len=32, alpha=1, beta=2, rho=0.02, p_best=0.01, seed=1,
+                tabu="bitmask", pher="dense", ls_nn=0) -> mmas_params:
+    return mmas_params(n=n, ants=ants, cand_len=cand_len, alpha=alpha, beta=beta, rho=rho,
+                       p_best=p_best, seed=seed, tabu=TABU.get(tabu, tabu),
+                       pher_mode=PHER.get(pher, pher), ls_nn=ls_nn, reserved=0)
+
+
+def mmas_workspace_bytes(params: mmas_params) -> int:
+    return int(lib.mmas_workspace_bytes(C.byref(params)))
+
+
+_DTYPES = {
+    MMAS_BUF_DIST: np.int32, MMAS_BUF_PHEROMONE: np.float32, MMAS_BUF_CHOICE: np.float32,
+    MMAS_BUF_CHC: np.float32, MMAS_BUF_CAND: np.uint16, MMAS_BUF_HEUR: np.float32,
+    MMAS_BUF_TOURS: np.uint16, MMAS_BUF_LENGTHS: np.int64, MMAS_BUF_GB_TOUR: np.uint16,
+    MMAS_BUF_NN_TOUR: np.uint16, MMAS_BUF_FALLBACK: np.int64, MMAS_BUF_LSNN: np.uint16,
+}
+
+
+class Colony:
+    """One context: a distance matrix, its parameters and a torch-owned workspace."""
+
+    def __init__(self, dist, ants, cand_len=32, alpha=1, beta=2, rho=0.02, p_best=0.01, seed=1,
+                 tabu="bitmask", pher="dense", ls_nn=0, device=None, stream=None):
+        import torch
+
+        d = np.ascontiguousarray(dist, dtype=np.int32)
+        if d.ndim != 2 or d.shape[0] != d.shape[1]:
+            raise ValueError("dist must be a square int32 matrix")
+        self.n = int(d.shape[0])
+        self.params = make_params(self.n, ants, cand_len, alpha, beta, rho, p_best, seed, tabu, pher, ls_nn)
+        self.ants = int(ants)
+        ws_bytes = mmas_workspace_bytes(self.params)
+        if ws_bytes == 0:
+            raise MmasError(MMAS_EINVAL, "mmas_workspace_bytes")
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._ctx = C.c_void_p()
+        with torch.cuda.device(self.device):
+            st = lib.mmas_create(d.ctypes.data_as(C.c_void_p), C.byref(self.params),
+                                 C.c_void_p(self.ws.data_ptr()), ws_bytes,
+                                 C.c_void_p(self.stream.cuda_stream), C.byref(self._ctx))
+        _check(st, "mmas_create")
+        self.cl = min(self.params.cand_len, self.n - 1)
+
+    # -- lifetime --
+    def close(self):
+        if getattr(self, "_ctx", None) and self._ctx.value:
+            lib.mmas_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- the per-iteration calls (Alg. 1) --
+    def prepare_choice_info(self):
+        _check(lib.mmas_prepare_choice_info(self._ctx), "mmas_prepare_choice_info")
+
+    def construct(self, iteration: int):
+        _check(lib.mmas_construct(self._ctx, iteration), "mmas_construct")
+
+    def two_opt(self):
+        _check(lib.mmas_two_opt(self._ctx), "mmas_two_opt")
+
+    def update_pheromone(self):
+        _check(lib.mmas_update_pheromone(self._ctx), "mmas_update_pheromone")
+
+    def iterate(self, iteration: int):
+        self.prepare_choice_info()
+        self.construct(iteration)
+        if self.params.ls_nn > 0:
+            self.two_opt()
+        self.update_pheromone()
+
+    def synchronize(self):
+        _check(lib.mmas_synchronize(self._ctx), "mmas_synchronize")
+
+    # -- results --
+    def best(self):
+        t = np.zeros(self.n, dtype=np.int32)
+        length = C.c_int64()
+        _check(lib.mmas_best(self._ctx, t.ctypes.data_as(C.c_void_p), C.byref(length)), "mmas_best")
+        return (t if length.value >= 0 else None), int(length.value)
+
+    def buffer(self, which: int):
+        """(device pointer, bytes) of a workspace view."""
+        ptr = C.c_void_p()
+        nbytes = C.c_size_t()
+        _check(lib.mmas_buffer(self._ctx, which, C.byref(ptr), C.byref(nbytes)), "mmas_buffer")
+        return ptr.value, int(nbytes.value)
+
+    def tensor(self, which: int):
+        """A torch view (no copy) of a workspace buffer."""
+        import torch
+
+        ptr, nbytes = self.buffer(which)
+        if nbytes == 0:
+            return None
+        off = ptr - self.ws.data_ptr()
+        tdt = {np.int32: torch.int32, np.float32: torch.float32, np.uint16: torch.uint16,
+               np.int64: torch.int64}[_DTYPES[which]]
+        return self.ws[off:off + nbytes].view(tdt)
+
+    def read(self, which: int) -> np.ndarray:
+        _, nbytes = self.buffer(which)
+        if which == MMAS_BUF_STATE:
+            st = mmas_device_state()
+            _check(lib.mmas_read(self._ctx, which, C.byref(st), nbytes), "mmas_read")
+            return st
+        out = np.empty(nbytes // np.dtype(_DTYPES[which]).itemsize, dtype=_DTYPES[which])
+        _check(lib.mmas_read(self._ctx, which, out.ctypes.data_as(C.c_void_p), nbytes), "mmas_read")
+        return out
+
+    def set_pheromone(self, tau):
+        t = np.ascontiguousarray(tau, dtype=np.float32).reshape(-1)
+        _, nbytes = self.buffer(MMAS_BUF_PHEROMONE)
+        if t.nbytes != nbytes:
+            raise ValueError("pheromone has the wrong size")
+        _check(lib.mmas_set_pheromone(self._ctx, t.ctypes.data_as(C.c_void_p)), "mmas_set_pheromone")
+
+    # convenience views
+    def tours(self):
+        return self.read(MMAS_BUF_TOURS).reshape(self.ants, self.n)
+
+    def lengths(self):
+        return self.read(MMAS_BUF_LENGTHS)
+
+    def pheromone(self):
+        return self.read(MMAS_BUF_PHEROMONE).reshape(self.n, -1)
+
+    def choice(self):
+        return self.read(MMAS_BUF_CHOICE).reshape(self.n, self.n)
+
+    def chc(self):
+        return self.read(MMAS_BUF_CHC).reshape(self.n, self.cl)
+
+    def cand(self):
+        return self.read(MMAS_BUF_CAND).reshape(self.n, self.cl)
+
+    def fallback(self):
+        f = self.read(MMAS_BUF_FALLBACK)
+        return f[: self.ants], f[self.ants:]
+
+    def state(self):
+        return self.read(MMAS_BUF_STATE)
+
+    def limits(self):
+        st = self.state()
+        return np.float32(st.tau_min), np.float32(st.tau_max)
