@@ -66,8 +66,14 @@ def main():
     ap.add_argument("--workload", default="clustered1002")
     ap.add_argument("--tabu", default="bitmask", choices=["bitmask", "compact"])
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--ants", type=int, default=0, help="override the workload's ant count")
+    ap.add_argument("--ants-per-block", type=int, default=0)
+    ap.add_argument("--table-rows", type=int, default=-1)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB (3 times) and exit; "
+                         "its FETCH_SIZE / WRITE_SIZE calibrate the HBM traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the method's "
@@ -80,10 +86,21 @@ def main():
     from paper_2003_11902_amd import mmas as M
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy_mib:
+        src = torch.ones(args.calibrate_copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": src.numel() * 4}), flush=True)
+        return
     xy, dist, w = I.workload_instance(args.workload)
+    if args.ants:
+        w["ants"] = args.ants
     n = w["n"]
     col = M.Colony(dist, w["ants"], cand_len=w["cand_len"], alpha=w["alpha"], beta=w["beta"],
                    rho=w["rho"], seed=args.seed, tabu=args.tabu, pher=w["pher"], ls_nn=w["ls_nn"])
+    col.set_launch(args.ants_per_block, args.table_rows)
     stream = col.stream
 
     def step(it):
@@ -139,7 +156,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "ants": w["ants"], "cand_len": w["cand_len"],
                    "alpha": w["alpha"], "beta": w["beta"], "rho": w["rho"], "tabu": args.tabu,
-                   "pheromone": w["pher"], "instance": f"{w['kind']} seed {w['seed']}"},
+                   "pheromone": w["pher"], "instance": f"{w['kind']} seed {w['seed']}",
+                   "ants_per_block": args.ants_per_block or 4, "table_rows": args.table_rows},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "k_construct", "kernel_ms": cons_ms,

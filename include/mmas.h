@@ -8,7 +8,7 @@
  * falling back to every unvisited node when the list is exhausted, with its
  * visited set in a bitmask tabu or the compact tabu (Sec. 4.1); then the
  * iteration best deposits pheromone after evaporation, within the trail limits
- * [tau_min, tau_max] (Sec. 3.1).
+ * [tau_min, tau_max] (Sec. 2.1).
  *
  * Conventions shared by every call:
  *  - Device memory: the caller owns one device buffer (the workspace, at
@@ -66,7 +66,8 @@ typedef struct mmas_params {
     int32_t pher_mode; /* MMAS_PHER_DENSE: n*n trails; MMAS_PHER_CANDIDATES: trails
                           stored only on the (i, cand[i][r]) edges, every other edge
                           held at tau_min (needs cand_len >= 1) */
-    int32_t ls_nn;     /* 2-opt neighbour-list length, 0 = no local search */
+    int32_t ls_nn;     /* 2-opt neighbour-list length 0..32 (the paper uses 32),
+                          0 = no local search */
     int32_t reserved;  /* must be 0 */
 } mmas_params;
 
@@ -111,9 +112,9 @@ size_t mmas_workspace_bytes(const mmas_params* p);
 
 /* Set-up (Alg. 1 before its loop). Copies `dist_host` (n*n int32, row-major,
  * host memory; the caller may free it on return) into the workspace, checks it
- * (symmetric, zero diagonal, positive elsewhere: Sec. 2 requires positive
- * distances and the deposit of Sec. 3.1 treats (i,j) and (j,i) as one edge),
- * and then on the GPU: eta = 1/d and eta^beta (Sec. 2), the candidate lists of
+ * (symmetric, zero diagonal, positive elsewhere: Sec. 2.1 requires positive
+ * distances and the deposit of Sec. 2.1 treats (i,j) and (j,i) as one edge),
+ * and then on the GPU: eta = 1/d and eta^beta (Sec. 2.1), the candidate lists of
  * the cl nearest cities by (distance, index) (Sec. 4.3), the 2-opt neighbour
  * lists, the nearest-neighbour tour from city 0 (ties to the lowest index),
  * the trail limits from its length (tau_max = 1/(rho C), tau_min =
@@ -125,7 +126,7 @@ size_t mmas_workspace_bytes(const mmas_params* p);
 mmas_status mmas_create(const int32_t* dist_host, const mmas_params* p, void* dev_ws,
                         size_t ws_bytes, void* hip_stream, mmas_ctx** out);
 
-/* choice_info = tau^alpha * eta^beta in FP32 (Sec. 3.1), dense and along the
+/* choice_info = tau^alpha * eta^beta in FP32 (Sec. 2.1), dense and along the
  * candidate lists. The pheromone update refreshes it as it writes tau, so this
  * launches only when tau changed in another way (set-up, mmas_set_pheromone). */
 mmas_status mmas_prepare_choice_info(mmas_ctx* ctx);
@@ -138,8 +139,16 @@ mmas_status mmas_prepare_choice_info(mmas_ctx* ctx);
  * the same rule. Writes MMAS_BUF_TOURS, MMAS_BUF_LENGTHS, MMAS_BUF_FALLBACK. */
 mmas_status mmas_construct(mmas_ctx* ctx, uint32_t iteration);
 
+/* Launch shape of the construction kernel; results never depend on it.
+ * `ants_per_block`: ants (one wave64 each) per workgroup, 1, 2, 4, 8 or 16
+ * (0 = default 4; fewer are used if their LDS does not fit). `table_rows`:
+ * how many rows of the candidate table (ids and choice_info) each workgroup
+ * stages in LDS: -1 = as many as fit (default), 0 = none, k = at most k.
+ * EINVAL for other values. */
+mmas_status mmas_set_launch(mmas_ctx* ctx, int32_t ants_per_block, int32_t table_rows);
+
 /* 2-opt on every ant's tour with ls_nn-nearest-neighbour lists and don't-look
- * bits (Sec. 5.5), as a sequential first-improvement search (cities in index
+ * bits (Sec. 5.7), as a sequential first-improvement search (cities in index
  * order, successor direction before predecessor, neighbours by rank while the
  * first partial gain is positive; the shorter path is reversed). Updates
  * tours and lengths. EUNSUPPORTED if ls_nn == 0; ESTATE before a construct. */
@@ -173,6 +182,55 @@ mmas_status mmas_synchronize(mmas_ctx* ctx);
 
 /* Frees the context (not the workspace). NULL is a no-op. */
 void mmas_destroy(mmas_ctx* ctx);
+
+/* ---- batches ------------------------------------------------------------
+ * Many instances (uneven n) advance one iteration of Alg. 1 per step for all
+ * of them at once: one persistent construction launch pulling (instance,
+ * group of ants) tiles from a queue ordered by decreasing n, one launch for
+ * every instance's iteration best / global best / limits, one launch for the
+ * fused update of every row. The iteration number lives in device memory, so
+ * a step can be captured once into a hipGraph and replayed. Instance i gets
+ * exactly the tours and trails of a single context with params[i] driven with
+ * iterations 0, 1, 2, ... */
+typedef struct mmas_batch mmas_batch;
+
+/* Workspace bytes for `count` instances (params[i].n gives the size of the
+ * i-th distance matrix). EINVAL if any parameters are invalid. */
+mmas_status mmas_batch_workspace_bytes(int32_t count, const mmas_params* params, size_t* bytes);
+
+/* Set-up of every instance (as mmas_create) inside one workspace.
+ * `dists_host[i]` is instance i's n_i*n_i int32 matrix (host, copied). All
+ * instances must share `tabu` and `pher_mode`; ls_nn must be 0
+ * (EUNSUPPORTED otherwise). `hip_stream` should not be the null stream if the
+ * step is to be captured. Synchronises. */
+mmas_status mmas_batch_create(int32_t count, const int32_t* const* dists_host, const mmas_params* params,
+                              void* dev_ws, size_t ws_bytes, void* hip_stream, mmas_batch** out);
+
+/* Launch shape of the batched construction (results never depend on it):
+ * `ants_per_block` 1, 2, 4, 8 or 16 ants (waves) per workgroup, and
+ * `table_bytes` of LDS per workgroup for the candidate table (-1 = all that
+ * is left after the ants' regions). Drops a captured graph. */
+mmas_status mmas_batch_set_launch(mmas_batch* b, int32_t ants_per_block, int32_t table_bytes);
+
+/* Autotuner: times one construction launch for each ants_per_block in
+ * {4, 8, 16} with the LDS table on and off, keeps the fastest and reports it.
+ * Trails are not touched. Synchronises; drops a captured graph. */
+mmas_status mmas_batch_tune(mmas_batch* b, int32_t* ants_per_block, int32_t* table_bytes);
+
+/* Captures one step into a hipGraph; later steps replay it. */
+mmas_status mmas_batch_capture(mmas_batch* b);
+
+/* One iteration for every instance (graph replay if captured). */
+mmas_status mmas_batch_step(mmas_batch* b);
+
+/* Number of completed steps (synchronises). */
+mmas_status mmas_batch_iteration(mmas_batch* b, uint32_t* iteration);
+
+/* The context of instance `index` (owned by the batch), for mmas_read,
+ * mmas_best and mmas_buffer. Do not drive it with the per-iteration calls. */
+mmas_status mmas_batch_context(mmas_batch* b, int32_t index, mmas_ctx** ctx);
+
+void mmas_batch_destroy(mmas_batch* b);
 
 /* Diagnostics, for checking the device arithmetic against an independent
  * implementation: the device FP32 logarithm of `count` values in (0,1)

@@ -131,7 +131,7 @@ static float powi_f32(float x, int k) {
     return r;
 }
 
-/* eta_ij^beta with eta = 1/d (Sec. 2) */
+/* eta_ij^beta with eta = 1/d (Sec. 2.1) */
 static float heur_of(int32_t d, int beta) {
     float eta = 1.0f / (float)d;
     return powi_f32(eta, beta);
@@ -210,7 +210,7 @@ int64_t orc_nn_tour(int n, const int32_t* dist, uint16_t* tour) {
 }
 
 /* ------------------------------------------------------------------------
- * 2-opt with neighbour lists and don't-look bits (Sec. 5.5, after Bentley),
+ * 2-opt with neighbour lists and don't-look bits (Sec. 5.7, after Bentley),
  * as a sequential first-improvement search:
  *  - cities are examined in index order, cyclically, skipping those whose
  *    don't-look bit is set; the search ends when every bit is set;
@@ -402,7 +402,7 @@ void orc_destroy(orc_colony* c) {
     free(c);
 }
 
-/* choice_info = tau^alpha * eta^beta (Sec. 3.1), along the candidate lists too */
+/* choice_info = tau^alpha * eta^beta (Sec. 2.1), along the candidate lists too */
 void orc_prepare_choice(orc_colony* c) {
     int n = c->n, cl = c->cl;
     if (c->pher_mode == ORC_PHER_DENSE) {

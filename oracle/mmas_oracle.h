@@ -10,7 +10,7 @@
  * Everything follows the paper's method in its own order (Alg. 1 for the main
  * loop, Eq. (1) for the selection distribution, Alg. 4 / Sec. 4.2.2 for the
  * weighted-reservoir-sampling selection with logarithmic keys, Sec. 4.3 for
- * candidate lists, Sec. 3.1 for evaporation, deposit and the trail limits),
+ * candidate lists, Sec. 2.1 for evaporation, deposit and the trail limits),
  * with every random draw taken from a counter-based generator so that one
  * (instance, parameters, seed) has exactly one correct result.
  *
@@ -66,7 +66,7 @@ enum { ORC_PHER_DENSE = 0, ORC_PHER_CANDIDATES = 1 };
 typedef struct orc_colony orc_colony;
 
 /* Builds the colony state for one instance and runs the set-up steps of
- * Alg. 1 before its main loop: eta = 1/d (Sec. 2), the candidate lists
+ * Alg. 1 before its main loop: eta = 1/d (Sec. 2.1), the candidate lists
  * (Sec. 4.3), the nearest-neighbour tour, the trail limits from its length
  * and tau <- tau_max. `dist` (n*n, row-major, int32) is copied.
  * alpha and beta are small non-negative integers. rho is the evaporation

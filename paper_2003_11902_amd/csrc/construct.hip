@@ -19,6 +19,7 @@ namespace mmas {
 namespace {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr size_t kDrawBytes = 4 * kWave * sizeof(float);  // candidate draws of the next steps
 
 // ---- tabu variants ---------------------------------------------------------
 
@@ -100,64 +101,99 @@ __device__ __forceinline__ void keep_best(uint32_t code, uint32_t node, uint32_t
     }
 }
 
-// All-node fallback over the bitmask: lane l takes the slot groups
-// g = cl/4 + l, + 64, ...; group g holds slots 4g..4g+3, i.e. cities
-// 4g - cl .. 4g - cl + 3, and one Philox block serves all four.
-template <class W>
-__device__ uint32_t fallback(const BitmaskTabu& tabu, const W& weight, int n, int cl, uint64_t seed,
-                             uint32_t it, uint32_t ant, uint32_t step, int lane) {
-    uint32_t bcode = 0u, bnode = kNone;
-    const int g0 = cl >> 2, g1 = (cl + n - 1) >> 2;
-    for (int g = g0 + lane; g <= g1; g += kWave) {
-        const int v0 = 4 * g - cl;
-        bool any = false;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int v = v0 + j;
-            any |= (v >= 0 && v < n && !tabu.visited((uint32_t)v));
+// The unvisited cities of a bitmask tabu, gathered into `list` (LDS, one
+// 16-bit entry per city; any order). Returns their number.
+__device__ int gather_unvisited(const BitmaskTabu& tabu, int n, uint16_t* list, int lane) {
+    const int words = (n + 31) >> 5;
+    int total = 0;
+    for (int w0 = 0; w0 < words; w0 += kWave) {
+        const int wi = w0 + lane;
+        uint32_t fr = 0u;
+        if (wi < words) {
+            fr = ~tabu.bits[wi];
+            if (wi == words - 1 && (n & 31)) fr &= (1u << (n & 31)) - 1u;
         }
-        if (!any) continue;
-        const Words4 blk = draw_block(seed, it, ant, step, (uint32_t)(4 * g));
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int v = v0 + j;
-            if (v < 0 || v >= n || tabu.visited((uint32_t)v)) continue;
-            const float key = log_u01(u01(blk.w[j])) / weight((uint32_t)v);
-            keep_best(ord_key(key), (uint32_t)v, bcode, bnode);
+        const int c = __popc(fr);
+        int inc = c;  // inclusive prefix sum of the counts over the wave
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
         }
+        int p = total + inc - c;
+        while (fr) {
+            const int b = __ffs(fr) - 1;
+            fr &= fr - 1u;
+            list[p++] = (uint16_t)(wi * 32 + b);
+        }
+        total += __shfl(inc, kWave - 1);
     }
-    return wave_select(bcode, bnode);
+    return total;
 }
 
-// All-node fallback over the compact tabu: the left part lists exactly the
-// unvisited cities; each draws its own slot cl + v.
+// All-node fallback over a list of the L unvisited cities: city v draws slot
+// cl + v. Each lane takes four list entries per round and issues their weight
+// loads before the Philox and logarithm work, so the loads overlap it.
 template <class W>
-__device__ uint32_t fallback(const CompactTabu& tabu, const W& weight, int /*n*/, int cl, uint64_t seed,
-                             uint32_t it, uint32_t ant, uint32_t step, int lane) {
+__device__ uint32_t fallback_list(const uint16_t* list, int L, const W& weight, int cl, uint64_t seed, uint32_t it,
+                                  uint32_t ant, uint32_t step, int lane) {
     uint32_t bcode = 0u, bnode = kNone;
-    for (int i = lane; i < tabu.L; i += kWave) {
-        const uint32_t v = tabu.entries[i];
-        const uint32_t slot = (uint32_t)cl + v;
-        const Words4 blk = draw_block(seed, it, ant, step, slot);
-        const float key = log_u01(u01(pick_word(blk, slot & 3u))) / weight(v);
-        keep_best(ord_key(key), v, bcode, bnode);
+    for (int base = 0; base < L; base += 4 * kWave) {
+        uint32_t v[4];
+        float w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + u * kWave + lane;
+            v[u] = i < L ? (uint32_t)list[i] : kNone;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w[u] = v[u] != kNone ? weight(v[u]) : 1.0f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (v[u] == kNone) continue;
+            const uint32_t slot = (uint32_t)cl + v[u];
+            const Words4 blk = draw_block(seed, it, ant, step, slot);
+            const float key = log_u01(u01(pick_word(blk, slot & 3u))) / w[u];
+            keep_best(ord_key(key), v[u], bcode, bnode);
+        }
     }
-    return wave_select(bcode, bnode);
+    return wave_select<4>(bcode, bnode);
 }
 
+// LDS layout of one workgroup: the candidate table of cities 0..R-1 (ids,
+// then choice_info), then one region per ant (its draws, its tabu and, for
+// the bitmask, room to list the unvisited cities during a fallback).
+struct Lds {
+    int rows;          // R: rows of the candidate table held in LDS
+    int table_bytes;   // bytes of the table part (16-aligned)
+    int per_ant;       // bytes of one ant's region
+};
+
+__host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
+
+// The whole workgroup copies the first R rows of the candidate table (ids,
+// then choice_info) into LDS; the caller synchronises.
+__device__ void stage_table(const Views& vw, int cl, int R, uint16_t* tcand, float* tchc) {
+    const int ne = R * cl;
+    for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+        tcand[e] = vw.cand[e];
+        tchc[e] = vw.chc[e];
+    }
+}
+
+// One ant's tour (one wave64): start city, n - 1 selection steps, tour and
+// length stores. `region` is the ant's LDS region; rows 0..R-1 of the
+// candidate table are in LDS at tcand / tchc.
 template <int kTabu, int kPher>
-__global__ __launch_bounds__(256) void k_construct(Views vw, Shape s, uint32_t it, int ants_per_block,
-                                                   int lds_per_ant) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
-    const int ant = blockIdx.x * ants_per_block + wave;
-    if (wave >= ants_per_block || ant >= s.ants) return;  // whole waves leave together
-
+__device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int ant, int lane, uint8_t* region,
+                              const uint16_t* tcand, const float* tchc, int R) {
     const int n = s.n, cl = s.cl;
     const uint64_t seed = s.seed;
+
+    // per-ant LDS: the draws of the next steps (256 floats), then the tabu
+    float* lnbuf = reinterpret_cast<float*>(region);
     typename TabuOf<kTabu>::type tabu;
-    tabu.init(smem + (size_t)wave * lds_per_ant, n, lane);
+    tabu.init(region + kDrawBytes, n, lane);
+    uint16_t* ulist = reinterpret_cast<uint16_t*>(region + kDrawBytes + align16(4 * ((n + 31) / 32)));
 
     float tmin_a = 0.0f;
     if (kPher == MMAS_PHER_CANDIDATES) tmin_a = powi(vw.state->tau_min, s.alpha);
@@ -166,6 +202,14 @@ __global__ __launch_bounds__(256) void k_construct(Views vw, Shape s, uint32_t i
     const uint32_t x0 = draw_block(seed, it, (uint32_t)ant, 0u, 0u).w[0];
     const uint32_t start = (uint32_t)(((uint64_t)x0 * (uint64_t)n) >> 32);
     tabu.mark(start, lane);
+
+    // Candidate draws are generated ahead, S steps at a time: lane l computes
+    // the Philox block of step k + l/G and slots 4(l%G)..4(l%G)+3 and stores
+    // their logarithms at lnbuf[4l..4l+3]; step k + j then reads slot r at
+    // lnbuf[4jG + r]. G = 4-slot groups per step (a power of two), S = 64/G.
+    const int gsh = cl <= 4 ? 0 : cl <= 8 ? 1 : cl <= 16 ? 2 : cl <= 32 ? 3 : 4;
+    const int G = 1 << gsh;
+    const int S = kWave >> gsh;
 
     uint16_t* tour_out = vw.tours + (size_t)ant * n;
     const int32_t* dist = vw.dist;
@@ -179,26 +223,58 @@ __global__ __launch_bounds__(256) void k_construct(Views vw, Shape s, uint32_t i
         uint32_t next = kNone;
         if (cl > 0) {
             // candidate phase: lane r holds rank r of cur's list
-            uint32_t code = 0u, node = kNone;
+            uint32_t node = 0u;  // lanes past the list look at city 0 and get no key
+            float w = 0.0f;
             if (lane < cl) {
-                const size_t e = (size_t)cur * cl + lane;
-                node = vw.cand[e];
-                const float w = vw.chc[e];
-                const Words4 blk = draw_block(seed, it, (uint32_t)ant, (uint32_t)k, (uint32_t)lane);
-                const float lnu = log_u01(u01(pick_word(blk, (uint32_t)lane & 3u)));
-                if (!tabu.visited(node)) code = ord_key(lnu / w);
+                const int e = (int)cur * cl + lane;
+                if ((int)cur < R) {
+                    node = tcand[e];
+                    w = tchc[e];
+                } else {
+                    node = vw.cand[e];
+                    w = vw.chc[e];
+                }
             }
-            next = wave_select(code, node);
+            const int j = (k - 1) & (S - 1);
+            if (j == 0) {
+                const int ks = k + (lane >> gsh);
+                if (ks < n) {
+                    const Words4 b = draw_block(seed, it, (uint32_t)ant, (uint32_t)ks,
+                                                (uint32_t)(4 * (lane & (G - 1))));
+                    float4 lv;
+                    lv.x = log_u01(u01(b.w[0]));
+                    lv.y = log_u01(u01(b.w[1]));
+                    lv.z = log_u01(u01(b.w[2]));
+                    lv.w = log_u01(u01(b.w[3]));
+                    *reinterpret_cast<float4*>(lnbuf + 4 * lane) = lv;
+                }
+            }
+            // branch-free: every lane of the list computes its key; visited
+            // cities and lanes past the list contribute no key
+            const float lnu = lnbuf[4 * j * G + (lane & (4 * G - 1))];
+            const float key = lnu / w;
+            const bool live = lane < cl && !tabu.visited(node);
+            const uint32_t code = live ? ord_key(key) : 0u;
+            next = cl <= 32 ? wave_select<2>(code, node) : wave_select<4>(code, node);
         }
         if (next == kNone) {
             fb_steps += 1;
             fb_nodes += n - k;
+            const uint16_t* list;
+            int L;
+            if constexpr (kTabu == MMAS_TABU_BITMASK) {
+                L = gather_unvisited(tabu, n, ulist, lane);
+                list = ulist;
+            } else {
+                L = tabu.L;
+                list = tabu.entries;
+            }
             if constexpr (kPher == MMAS_PHER_DENSE) {
                 const DenseWeight wt{vw.choice + (size_t)cur * n};
-                next = fallback(tabu, wt, n, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+                next = fallback_list(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
             } else {
                 const CandWeight wt{dist + (size_t)cur * n, tmin_a, s.beta};
-                next = fallback(tabu, wt, n, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+                next = fallback_list(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
             }
         }
         if (next >= (uint32_t)n) {
@@ -234,27 +310,158 @@ __global__ __launch_bounds__(256) void k_construct(Views vw, Shape s, uint32_t i
 }
 
 template <int kTabu, int kPher>
+__global__ __launch_bounds__(1024) void k_construct(Views vw, Shape s, uint32_t it, int ants_per_block, Lds lds) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int R = lds.rows;
+    uint16_t* tcand = reinterpret_cast<uint16_t*>(smem);
+    float* tchc = reinterpret_cast<float*>(smem + align16(R * s.cl * 2));
+    if (R > 0) {
+        stage_table(vw, s.cl, R, tcand, tchc);
+        __syncthreads();
+    }
+    const int ant = blockIdx.x * ants_per_block + wave;
+    if (ant >= s.ants) return;  // whole waves leave together
+    construct_ant<kTabu, kPher>(vw, s, it, ant, lane, smem + lds.table_bytes + (size_t)wave * lds.per_ant, tcand,
+                                tchc, R);
+}
+
+// Batched construction: a persistent grid pulls tiles (instance, first ant of
+// a group of ants_per_block ants) from a queue ordered by decreasing n. Each
+// tile stages as many candidate rows of its instance as fit in the table part
+// of LDS, then every wave builds one ant's tour.
+template <int kTabu, int kPher>
+__global__ __launch_bounds__(1024) void k_batch_construct(const BatchItem* __restrict__ items,
+                                                          const BatchTile* __restrict__ tiles, int ntiles,
+                                                          uint32_t* __restrict__ queue, const uint32_t* __restrict__ it_dev,
+                                                          int ants_per_block, int table_bytes, int per_ant) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ int s_tile;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const uint32_t it = *it_dev;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int t = s_tile;
+        if (t >= ntiles) break;  // every wave of the workgroup leaves here
+        const BatchTile tile = tiles[t];
+        const Views vw = items[tile.inst].v;
+        const Shape s = items[tile.inst].s;
+        int R = 0;
+        if (s.cl > 0) {
+            R = (table_bytes - 16) / (s.cl * 6);
+            if (R > s.n) R = s.n;
+            while (R > 0 && align16(R * s.cl * 2) + R * s.cl * 4 > table_bytes) --R;
+        }
+        uint16_t* tcand = reinterpret_cast<uint16_t*>(smem);
+        float* tchc = reinterpret_cast<float*>(smem + align16(R * s.cl * 2));
+        if (R > 0) stage_table(vw, s.cl, R, tcand, tchc);
+        __syncthreads();
+        const int ant = tile.ant0 + wave;
+        if (ant < s.ants)
+            construct_ant<kTabu, kPher>(vw, s, it, ant, lane, smem + table_bytes + (size_t)wave * per_ant, tcand,
+                                        tchc, R);
+        __syncthreads();  // the next tile reuses the table part
+    }
+}
+
+}  // namespace
+
+int max_lds_per_block() {
+    static int cached = -1;
+    if (cached < 0) {
+        int dev = 0, v = 65536;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+            cached = v;
+        else
+            cached = 65536;
+    }
+    return cached;
+}
+
+namespace {
+
+template <int kTabu, int kPher>
 hipError_t launch_t(const Views& v, const Shape& s, uint32_t it, hipStream_t st) {
-    const size_t per_ant = construct_lds_per_ant(s);
-    int apb = 4;
-    while (apb > 1 && per_ant * apb > 64 * 1024) --apb;
-    const size_t lds = per_ant * apb;
+    const int per_ant = (int)construct_lds_per_ant(s);
+    const int budget = max_lds_per_block();
+    int apb = s.ants_per_block > 0 ? s.ants_per_block : 4;
+    while (apb > 1 && per_ant * apb > budget) --apb;
+    if (per_ant * apb > budget) return hipErrorInvalidValue;
+    // as many rows of the candidate table as fit next to the ants' regions
+    Lds lds{};
+    lds.per_ant = per_ant;
+    const int row_bytes = s.cl * 6;
+    int rows = 0;
+    if (s.cl > 0) {
+        rows = (budget - apb * per_ant - 32) / row_bytes;
+        if (rows > s.n) rows = s.n;
+        if (s.table_rows >= 0 && rows > s.table_rows) rows = s.table_rows;
+        while (rows > 0 && align16(rows * s.cl * 2) + align16(rows * s.cl * 4) + apb * per_ant > budget) --rows;
+        if (rows < 0) rows = 0;
+    }
+    lds.rows = rows;
+    lds.table_bytes = align16(rows * s.cl * 2) + align16(rows * s.cl * 4);
+    const size_t bytes = (size_t)lds.table_bytes + (size_t)apb * per_ant;
     auto kern = k_construct<kTabu, kPher>;
-    if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (bytes > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
     }
     const int blocks = (s.ants + apb - 1) / apb;
-    kern<<<blocks, 64 * apb, lds, st>>>(v, s, it, apb, (int)per_ant);
+    kern<<<blocks, 64 * apb, bytes, st>>>(v, s, it, apb, lds);
     return hipGetLastError();
 }
 
 }  // namespace
 
 size_t construct_lds_per_ant(const Shape& s) {
-    size_t b = s.tabu == MMAS_TABU_BITMASK ? sizeof(uint32_t) * (size_t)((s.n + 31) / 32)
-                                           : sizeof(uint16_t) * (size_t)s.n;
-    return (b + 15) & ~(size_t)15;
+    // draws; tabu (bitmask words, or compact entries); for the bitmask, the
+    // list of unvisited cities built in a fallback
+    const int bits = align16(4 * ((s.n + 31) / 32));
+    const int list = align16(2 * s.n);
+    return kDrawBytes + (s.tabu == MMAS_TABU_BITMASK ? bits + list : list);
+}
+
+hipError_t launch_batch_construct(const BatchItem* items, const BatchTile* tiles, int ntiles, uint32_t* queue,
+                                  const uint32_t* it_dev, int tabu, int pher, int ants_per_block, int table_bytes,
+                                  int per_ant, int grid, hipStream_t st) {
+    const size_t bytes = (size_t)table_bytes + (size_t)ants_per_block * per_ant;
+    const void* kern;
+    if (tabu == MMAS_TABU_BITMASK)
+        kern = pher == MMAS_PHER_DENSE ? (const void*)k_batch_construct<MMAS_TABU_BITMASK, MMAS_PHER_DENSE>
+                                       : (const void*)k_batch_construct<MMAS_TABU_BITMASK, MMAS_PHER_CANDIDATES>;
+    else
+        kern = pher == MMAS_PHER_DENSE ? (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_DENSE>
+                                       : (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_CANDIDATES>;
+    // the LDS limit was raised by batch_construct_grid for this footprint (a
+    // graph capture must not need it here)
+    void* args[] = {(void*)&items, (void*)&tiles, (void*)&ntiles, (void*)&queue, (void*)&it_dev,
+                    (void*)&ants_per_block, (void*)&table_bytes, (void*)&per_ant};
+    return hipLaunchKernel(kern, dim3(grid), dim3(64 * ants_per_block), args, bytes, st);
+}
+
+int batch_construct_grid(int tabu, int pher, int ants_per_block, int lds_bytes) {
+    const void* kern;
+    if (tabu == MMAS_TABU_BITMASK)
+        kern = pher == MMAS_PHER_DENSE ? (const void*)k_batch_construct<MMAS_TABU_BITMASK, MMAS_PHER_DENSE>
+                                       : (const void*)k_batch_construct<MMAS_TABU_BITMASK, MMAS_PHER_CANDIDATES>;
+    else
+        kern = pher == MMAS_PHER_DENSE ? (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_DENSE>
+                                       : (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_CANDIDATES>;
+    if (lds_bytes > 64 * 1024 &&
+        hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes) != hipSuccess)
+        return 0;
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * ants_per_block, lds_bytes) != hipSuccess)
+        return 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return per_cu * cus;
 }
 
 hipError_t launch_construct(const Views& v, const Shape& s, uint32_t it, hipStream_t st) {

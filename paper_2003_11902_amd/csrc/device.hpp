@@ -24,16 +24,15 @@ __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
                                                 uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo0 = 0xD2511F53u * c0;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
-        const uint32_t lo1 = 0xCD9E8D57u * c2;
-        const uint32_t n0 = hi1 ^ c1 ^ k0;
-        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        // one 32x32 -> 64-bit multiply each (v_mad_u64_u32) gives hi and lo
+        const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
         c0 = n0;
-        c1 = lo1;
+        c1 = (uint32_t)p1;
         c2 = n2;
-        c3 = lo0;
+        c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -120,28 +119,30 @@ __device__ __forceinline__ uint32_t dpp(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, kCtrl, 0xF, 0xF, false);
 }
 
+// kRows = number of 16-lane rows that hold data (2 for lanes 0..31, 4 for
+// the whole wave).
+template <int kRows = 4>
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
     x = max(x, dpp<0xB1>(x));   // quad_perm [1,0,3,2]
     x = max(x, dpp<0x4E>(x));   // quad_perm [2,3,0,1]
     x = max(x, dpp<0x141>(x));  // row_half_mirror
     x = max(x, dpp<0x140>(x));  // row_mirror
-    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 0);
-    const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)x, 16);
-    const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)x, 32);
-    const uint32_t r3 = (uint32_t)__builtin_amdgcn_readlane((int)x, 48);
-    return max(max(r0, r1), max(r2, r3));
+    uint32_t r = max((uint32_t)__builtin_amdgcn_readlane((int)x, 0), (uint32_t)__builtin_amdgcn_readlane((int)x, 16));
+    if (kRows == 4)
+        r = max(r, max((uint32_t)__builtin_amdgcn_readlane((int)x, 32), (uint32_t)__builtin_amdgcn_readlane((int)x, 48)));
+    return r;
 }
 
+template <int kRows = 4>
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
     x = min(x, dpp<0xB1>(x));
     x = min(x, dpp<0x4E>(x));
     x = min(x, dpp<0x141>(x));
     x = min(x, dpp<0x140>(x));
-    const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)x, 0);
-    const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)x, 16);
-    const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)x, 32);
-    const uint32_t r3 = (uint32_t)__builtin_amdgcn_readlane((int)x, 48);
-    return min(min(r0, r1), min(r2, r3));
+    uint32_t r = min((uint32_t)__builtin_amdgcn_readlane((int)x, 0), (uint32_t)__builtin_amdgcn_readlane((int)x, 16));
+    if (kRows == 4)
+        r = min(r, min((uint32_t)__builtin_amdgcn_readlane((int)x, 32), (uint32_t)__builtin_amdgcn_readlane((int)x, 48)));
+    return r;
 }
 
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t x) {
@@ -152,15 +153,16 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t x) {
 // Argmax of (key code, -node) over the wave: the node with the largest key,
 // the lowest node among equal keys. `code` is 0 for lanes without a key.
 // Returns the node, or 0xFFFFFFFF if no lane had a key.
+template <int kRows = 4>
 __device__ __forceinline__ uint32_t wave_select(uint32_t code, uint32_t node) {
-    const uint32_t best = wave_max_u32(code);
+    const uint32_t best = wave_max_u32<kRows>(code);
     if (best == 0u) return 0xFFFFFFFFu;
     const uint64_t tied = __ballot(code == best);
     if (__popcll(tied) == 1) {
         const int lane = __ffsll((unsigned long long)tied) - 1;
         return (uint32_t)__builtin_amdgcn_readlane((int)node, lane);
     }
-    return wave_min_u32(code == best ? node : 0xFFFFFFFFu);
+    return wave_min_u32<kRows>(code == best ? node : 0xFFFFFFFFu);
 }
 
 }  // namespace mmas

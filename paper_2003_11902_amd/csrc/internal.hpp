@@ -42,6 +42,21 @@ struct Shape {
     float rho;
     double pdec; // p_best^(1/n)
     uint64_t seed;
+    int ants_per_block;  // construction launch: ants (waves) per workgroup
+    int table_rows;      // rows of the candidate table staged in LDS (-1: all that fit)
+};
+
+// One instance of a batch (device array, one entry per instance).
+struct BatchItem {
+    Views v;
+    Shape s;
+};
+
+// One construction tile of a batch: ants ant0 .. ant0 + ants_per_block - 1
+// of instance `inst`.
+struct BatchTile {
+    int inst;
+    int ant0;
 };
 
 // ---- set-up (prep.hip) ----
@@ -54,8 +69,25 @@ hipError_t launch_init_trails(const Views& v, const Shape& s, hipStream_t st);
 // ---- per iteration ----
 hipError_t launch_choice(const Views& v, const Shape& s, hipStream_t st);             // update.hip
 hipError_t launch_construct(const Views& v, const Shape& s, uint32_t it, hipStream_t st); // construct.hip
-hipError_t launch_two_opt(const Views& v, const Shape& s, hipStream_t st);           // two_opt.hip
+hipError_t launch_two_opt_prepare(const Views& v, const Shape& s, int32_t* nnd, hipStream_t st);  // two_opt.hip
+hipError_t launch_two_opt(const Views& v, const Shape& s, const int32_t* nnd, hipStream_t st);
 hipError_t launch_update(const Views& v, const Shape& s, hipStream_t st);            // update.hip
+
+// ---- batches (one launch per step for all instances) ----
+// construct.hip: persistent construction over `ntiles` tiles; `queue` must be
+// 0 at launch (the batched best kernel re-arms it).
+hipError_t launch_batch_construct(const BatchItem* items, const BatchTile* tiles, int ntiles, uint32_t* queue,
+                                  const uint32_t* it_dev, int tabu, int pher, int ants_per_block, int table_bytes,
+                                  int per_ant, int grid, hipStream_t st);
+// Persistent-grid size for this LDS footprint (workgroups that fit at once).
+int batch_construct_grid(int tabu, int pher, int ants_per_block, int lds_bytes);
+// update.hip: best/limits for every instance (one workgroup each), then the
+// fused update of every row of every instance (`row_start` = prefix sums of
+// the instances' row counts, count + 1 entries); increments *it_dev and
+// re-arms *queue.
+hipError_t launch_batch_update(const BatchItem* items, int count, const int* row_start, int total_rows,
+                               uint32_t* it_dev, uint32_t* queue, hipStream_t st);
+int max_lds_per_block();
 
 // LDS bytes one ant needs in the construction kernel (0 if it cannot run).
 size_t construct_lds_per_ant(const Shape& s);

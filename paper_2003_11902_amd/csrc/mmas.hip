@@ -21,7 +21,7 @@ struct mmas_ctx {
     size_t ws_bytes;
     size_t off[MMAS_BUF_COUNT];
     size_t len[MMAS_BUF_COUNT];
-    size_t off_succ, off_pred;
+    size_t off_succ, off_pred, off_nnd;
     bool choice_stale;
     bool constructed;
 };
@@ -44,7 +44,7 @@ bool params_ok(const mmas_params* p) {
     if (p->pher_mode != MMAS_PHER_DENSE && p->pher_mode != MMAS_PHER_CANDIDATES) return false;
     const int cl = p->cand_len < p->n - 1 ? p->cand_len : p->n - 1;
     if (p->pher_mode == MMAS_PHER_CANDIDATES && cl == 0) return false;
-    if (p->ls_nn < 0 || p->ls_nn > 64 || p->ls_nn > p->n - 1) return false;
+    if (p->ls_nn < 0 || p->ls_nn > 32 || p->ls_nn > p->n - 1) return false;
     if (p->reserved != 0) return false;
     return true;
 }
@@ -62,11 +62,13 @@ Shape shape_of(const mmas_params* p) {
     s.rho = p->rho;
     s.pdec = std::pow(p->p_best, 1.0 / (double)p->n);
     s.seed = p->seed;
+    s.ants_per_block = 4;
+    s.table_rows = -1;
     return s;
 }
 
 // Byte sizes of every view, then their offsets (256-byte aligned).
-size_t layout(const Shape& s, size_t* off, size_t* len, size_t* off_succ, size_t* off_pred) {
+size_t layout(const Shape& s, size_t* off, size_t* len, size_t* off_succ, size_t* off_pred, size_t* off_nnd) {
     const size_t n = (size_t)s.n, cl = (size_t)s.cl, ants = (size_t)s.ants;
     const bool dense = s.pher == MMAS_PHER_DENSE;
     len[MMAS_BUF_DIST] = 4 * n * n;
@@ -91,6 +93,8 @@ size_t layout(const Shape& s, size_t* off, size_t* len, size_t* off_succ, size_t
     pos = align_up(pos + 2 * n);
     *off_pred = pos;
     pos = align_up(pos + 2 * n);
+    *off_nnd = pos;  // d(i, nn[i][r]) of the 2-opt lists
+    pos = align_up(pos + 4 * n * (size_t)s.ls_nn);
     return pos;
 }
 
@@ -103,13 +107,23 @@ mmas_status hip_status(hipError_t e) { return e == hipSuccess ? MMAS_OK : MMAS_E
 
 }  // namespace
 
+namespace mmas {
+// The device views and constants of a context (for batches).
+bool ctx_views(mmas_ctx* c, Views* v, Shape* s) {
+    if (!c) return false;
+    *v = c->v;
+    *s = c->s;
+    return true;
+}
+}  // namespace mmas
+
 extern "C" {
 
 size_t mmas_workspace_bytes(const mmas_params* p) {
     if (!params_ok(p)) return 0;
     Shape s = shape_of(p);
-    size_t off[MMAS_BUF_COUNT], len[MMAS_BUF_COUNT], os, op;
-    return layout(s, off, len, &os, &op);
+    size_t off[MMAS_BUF_COUNT], len[MMAS_BUF_COUNT], os, op, od;
+    return layout(s, off, len, &os, &op, &od);
 }
 
 mmas_status mmas_create(const int32_t* dist_host, const mmas_params* p, void* dev_ws, size_t ws_bytes,
@@ -126,7 +140,7 @@ mmas_status mmas_create(const int32_t* dist_host, const mmas_params* p, void* de
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->ws = reinterpret_cast<char*>(dev_ws);
     c->ws_bytes = ws_bytes;
-    const size_t need = layout(s, c->off, c->len, &c->off_succ, &c->off_pred);
+    const size_t need = layout(s, c->off, c->len, &c->off_succ, &c->off_pred, &c->off_nnd);
     if (ws_bytes < need) {
         delete c;
         return MMAS_ENOSPACE;
@@ -138,7 +152,8 @@ mmas_status mmas_create(const int32_t* dist_host, const mmas_params* p, void* de
             delete c;
             return MMAS_EHIP;
         }
-        if (mmas::construct_lds_per_ant(s) > (size_t)maxlds) {
+        if (mmas::construct_lds_per_ant(s) > (size_t)maxlds ||
+            (s.ls_nn > 0 && mmas::two_opt_lds_bytes(s) > (size_t)maxlds)) {
             delete c;
             return MMAS_EUNSUPPORTED;
         }
@@ -168,6 +183,8 @@ mmas_status mmas_create(const int32_t* dist_host, const mmas_params* p, void* de
     if (e == hipSuccess) e = mmas::launch_nearest(v.dist, s.n, s.cl, v.cand, st);
     if (e == hipSuccess) e = mmas::launch_nearest(v.dist, s.n, s.ls_nn, v.lsnn, st);
     if (e == hipSuccess) e = mmas::launch_heuristic(v, s, st);
+    if (e == hipSuccess)
+        e = mmas::launch_two_opt_prepare(v, s, reinterpret_cast<int32_t*>(c->ws + c->off_nnd), st);
     if (e == hipSuccess) e = mmas::launch_nn_tour(v, s, st);
     if (e == hipSuccess) e = mmas::launch_init_trails(v, s, st);
     mmas_device_state hs;
@@ -206,12 +223,22 @@ mmas_status mmas_construct(mmas_ctx* c, uint32_t iteration) {
     return MMAS_OK;
 }
 
+mmas_status mmas_set_launch(mmas_ctx* c, int32_t ants_per_block, int32_t table_rows) {
+    if (!c) return MMAS_EINVAL;
+    if (ants_per_block != 0 && ants_per_block != 1 && ants_per_block != 2 && ants_per_block != 4 &&
+        ants_per_block != 8 && ants_per_block != 16)
+        return MMAS_EINVAL;
+    if (table_rows < -1) return MMAS_EINVAL;
+    c->s.ants_per_block = ants_per_block == 0 ? 4 : ants_per_block;
+    c->s.table_rows = table_rows;
+    return MMAS_OK;
+}
+
 mmas_status mmas_two_opt(mmas_ctx* c) {
     if (!c) return MMAS_EINVAL;
     if (c->s.ls_nn <= 0) return MMAS_EUNSUPPORTED;
     if (!c->constructed) return MMAS_ESTATE;
-    hipError_t e = mmas::launch_two_opt(c->v, c->s, c->stream);
-    if (e == hipErrorNotSupported) return MMAS_EUNSUPPORTED;
+    hipError_t e = mmas::launch_two_opt(c->v, c->s, reinterpret_cast<const int32_t*>(c->ws + c->off_nnd), c->stream);
     return hip_status(e);
 }
 

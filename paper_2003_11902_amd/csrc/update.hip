@@ -1,4 +1,4 @@
-// Per-iteration kernels around construction (Alg. 1, Sec. 3.1):
+// Per-iteration kernels around construction (Alg. 1, Sec. 2.1):
 //  - choice_info = tau^alpha * eta^beta, dense and along the candidate lists;
 //  - the iteration best, the global best and the trail limits (one workgroup);
 //  - evaporation, deposit on both directions of the iteration best's edges and
@@ -36,8 +36,9 @@ __global__ __launch_bounds__(256) void k_choice_cand(const float* __restrict__ t
 // Iteration best = shortest tour, lowest ant on ties. If it beats the global
 // best (or there is none yet), it becomes the global best and the limits are
 // recomputed from its length. Then the successor and predecessor of every
-// city along the iteration best, for the deposit.
-__global__ __launch_bounds__(1024) void k_best(Views vw, Shape s) {
+// city along the iteration best, for the deposit. One workgroup of any size
+// (a multiple of 64, at most 1024 threads).
+__device__ void best_and_limits(const Views& vw, const Shape& s) {
     __shared__ int64_t plen[16];
     __shared__ int32_t pant[16];
     __shared__ int s_ib;
@@ -100,6 +101,8 @@ __global__ __launch_bounds__(1024) void k_best(Views vw, Shape s) {
     }
 }
 
+__global__ __launch_bounds__(1024) void k_best(Views vw, Shape s) { best_and_limits(vw, s); }
+
 __device__ __forceinline__ float evaporate_deposit(float t, bool dep, float keep, float tmin, float tmax,
                                                    float delta) {
     float v = keep * t;
@@ -112,9 +115,8 @@ __device__ __forceinline__ float evaporate_deposit(float t, bool dep, float keep
 // dense: one workgroup per row i. The candidate entries of chc are computed
 // first from the old trails (each thread recomputes its entry's new value),
 // then the row is rewritten.
-__global__ __launch_bounds__(256) void k_update_dense(Views vw, Shape s) {
+__device__ void update_dense_row(const Views& vw, const Shape& s, size_t i) {
     const int n = s.n, cl = s.cl;
-    const size_t i = blockIdx.x;
     const mmas_device_state* st = vw.state;
     const float tmin = st->tau_min, tmax = st->tau_max, delta = st->delta;
     const float keep = 1.0f - s.rho;
@@ -133,6 +135,51 @@ __global__ __launch_bounds__(256) void k_update_dense(Views vw, Shape s) {
         trow[j] = t;
         crow[j] = powi(t, s.alpha) * hrow[j];
     }
+}
+
+// candidate-only trails, row i (its cl stored entries)
+__device__ void update_cand_row(const Views& vw, const Shape& s, size_t i) {
+    const mmas_device_state* st = vw.state;
+    const float tmin = st->tau_min, tmax = st->tau_max, delta = st->delta;
+    const float keep = 1.0f - s.rho;
+    const int si = vw.succ[i], pi = vw.pred[i];
+    for (int r = threadIdx.x; r < s.cl; r += blockDim.x) {
+        const size_t e = i * s.cl + r;
+        const int j = vw.cand[e];
+        const float t = evaporate_deposit(vw.tau[e], j == si || j == pi, keep, tmin, tmax, delta);
+        vw.tau[e] = t;
+        vw.chc[e] = powi(t, s.alpha) * vw.heur[e];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_update_dense(Views vw, Shape s) { update_dense_row(vw, s, blockIdx.x); }
+
+// batches: one workgroup per instance for the best, then one per row
+__global__ __launch_bounds__(1024) void k_batch_best(const BatchItem* __restrict__ items, uint32_t* it_dev,
+                                                     uint32_t* queue) {
+    best_and_limits(items[blockIdx.x].v, items[blockIdx.x].s);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *it_dev += 1u;  // construction of this iteration is done
+        *queue = 0u;    // re-arm the tile queue for the next construction
+    }
+}
+
+__global__ __launch_bounds__(256) void k_batch_update(const BatchItem* __restrict__ items, int count,
+                                                      const int* __restrict__ row_start) {
+    // instance of this row: last start <= blockIdx.x
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (row_start[mid] <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const Views vw = items[lo].v;
+    const Shape s = items[lo].s;
+    const size_t i = blockIdx.x - row_start[lo];
+    if (s.pher == MMAS_PHER_DENSE)
+        update_dense_row(vw, s, i);
+    else
+        update_cand_row(vw, s, i);
 }
 
 __global__ __launch_bounds__(256) void k_update_cand(Views vw, Shape s) {
@@ -165,6 +212,15 @@ hipError_t launch_choice(const Views& v, const Shape& s, hipStream_t st) {
         const size_t count = (size_t)s.n * s.cl;
         k_choice_cand<<<grid_for(count, 256), 256, 0, st>>>(v.tau, v.heur, count, s.alpha, v.chc);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_update(const BatchItem* items, int count, const int* row_start, int total_rows,
+                               uint32_t* it_dev, uint32_t* queue, hipStream_t st) {
+    k_batch_best<<<count, 256, 0, st>>>(items, it_dev, queue);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_batch_update<<<total_rows, 256, 0, st>>>(items, count, row_start);
     return hipGetLastError();
 }
 

@@ -11,7 +11,7 @@ uniformly over a square, and cities gathered in Gaussian clusters.
 
 Distances follow the usual Euclidean convention for integer instances,
 d = floor(sqrt(dx^2 + dy^2) + 0.5), computed in float64. The problem statement
-(Sec. 2) requires positive distances between distinct cities, so any city whose
+(Sec. 2.1) requires positive distances between distinct cities, so any city whose
 rounded distance to an earlier city is 0 is redrawn.
 """
 from __future__ import annotations

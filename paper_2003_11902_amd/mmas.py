@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libmmas.so")
+# MMAS_LIBRARY may point at another build of the same library (e.g. a debug
+# build); by default the in-tree build is used.
+LIB_PATH = os.environ.get("MMAS_LIBRARY") or os.path.join(HERE, "libmmas.so")
 
 # ---- constants mirrored from include/mmas.h --------------------------------
 MMAS_OK = 0
@@ -48,7 +50,10 @@ EXPORTED = (
     "mmas_workspace_bytes", "mmas_create", "mmas_prepare_choice_info", "mmas_construct",
     "mmas_two_opt", "mmas_update_pheromone", "mmas_best", "mmas_buffer", "mmas_read",
     "mmas_set_pheromone", "mmas_synchronize", "mmas_destroy", "mmas_status_str",
-    "mmas_eval_log", "mmas_eval_draws",
+    "mmas_eval_log", "mmas_eval_draws", "mmas_set_launch",
+    "mmas_batch_workspace_bytes", "mmas_batch_create", "mmas_batch_set_launch", "mmas_batch_tune",
+    "mmas_batch_capture", "mmas_batch_step", "mmas_batch_iteration", "mmas_batch_context",
+    "mmas_batch_destroy",
 )
 
 
@@ -89,6 +94,8 @@ def _load():
     for name in ("mmas_prepare_choice_info", "mmas_two_opt", "mmas_update_pheromone", "mmas_synchronize"):
         getattr(L, name).argtypes = [p]
         getattr(L, name).restype = C.c_int
+    L.mmas_set_launch.argtypes = [p, C.c_int32, C.c_int32]
+    L.mmas_set_launch.restype = C.c_int
     L.mmas_construct.argtypes = [p, C.c_uint32]
     L.mmas_construct.restype = C.c_int
     L.mmas_best.argtypes = [p, p, C.POINTER(C.c_int64)]
@@ -105,6 +112,23 @@ def _load():
     L.mmas_eval_log.restype = C.c_int
     L.mmas_eval_draws.argtypes = [C.c_uint64, p, p, p, p, p, C.c_size_t, p]
     L.mmas_eval_draws.restype = C.c_int
+    L.mmas_batch_workspace_bytes.argtypes = [C.c_int32, p, C.POINTER(C.c_size_t)]
+    L.mmas_batch_workspace_bytes.restype = C.c_int
+    L.mmas_batch_create.argtypes = [C.c_int32, p, p, p, C.c_size_t, p, C.POINTER(p)]
+    L.mmas_batch_create.restype = C.c_int
+    L.mmas_batch_set_launch.argtypes = [p, C.c_int32, C.c_int32]
+    L.mmas_batch_set_launch.restype = C.c_int
+    L.mmas_batch_tune.argtypes = [p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.mmas_batch_tune.restype = C.c_int
+    for name in ("mmas_batch_capture", "mmas_batch_step"):
+        getattr(L, name).argtypes = [p]
+        getattr(L, name).restype = C.c_int
+    L.mmas_batch_iteration.argtypes = [p, C.POINTER(C.c_uint32)]
+    L.mmas_batch_iteration.restype = C.c_int
+    L.mmas_batch_context.argtypes = [p, C.c_int32, C.POINTER(p)]
+    L.mmas_batch_context.restype = C.c_int
+    L.mmas_batch_destroy.argtypes = [p]
+    L.mmas_batch_destroy.restype = None
     L.mmas_status_str.argtypes = [C.c_int]
     L.mmas_status_str.restype = C.c_char_p
     return L
@@ -208,6 +232,9 @@ class Colony:
     def construct(self, iteration: int):
         _check(lib.mmas_construct(self._ctx, iteration), "mmas_construct")
 
+    def set_launch(self, ants_per_block=0, table_rows=-1):
+        _check(lib.mmas_set_launch(self._ctx, ants_per_block, table_rows), "mmas_set_launch")
+
     def two_opt(self):
         _check(lib.mmas_two_opt(self._ctx), "mmas_two_opt")
 
@@ -296,3 +323,83 @@ class Colony:
     def limits(self):
         st = self.state()
         return np.float32(st.tau_min), np.float32(st.tau_max)
+
+
+class _View(Colony):
+    """A context owned by a batch: read-only access through the Colony API."""
+
+    def __init__(self, handle, n, ants, params, ws, stream):
+        self._ctx = handle
+        self.n = n
+        self.ants = ants
+        self.params = params
+        self.ws = ws
+        self.stream = stream
+        self.cl = min(params.cand_len, n - 1)
+
+    def close(self):  # owned by the batch
+        self._ctx = C.c_void_p()
+
+
+class Batch:
+    """Many instances advancing together (mmas_batch_*)."""
+
+    def __init__(self, dists, params_list, device=None, stream=None):
+        import torch
+
+        self.count = len(dists)
+        self.dists = [np.ascontiguousarray(d, dtype=np.int32) for d in dists]
+        arr = (mmas_params * self.count)(*params_list)
+        self._params = arr
+        nbytes = C.c_size_t()
+        _check(lib.mmas_batch_workspace_bytes(self.count, arr, C.byref(nbytes)), "mmas_batch_workspace_bytes")
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        # a stream of its own (default priority): the null stream cannot be captured
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        ptrs = (C.c_void_p * self.count)(*[d.ctypes.data_as(C.c_void_p) for d in self.dists])
+        self._h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.mmas_batch_create(self.count, ptrs, arr, C.c_void_p(self.ws.data_ptr()), nbytes.value,
+                                         C.c_void_p(self.stream.cuda_stream), C.byref(self._h)),
+                   "mmas_batch_create")
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib.mmas_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_launch(self, ants_per_block=4, table_bytes=-1):
+        _check(lib.mmas_batch_set_launch(self._h, ants_per_block, table_bytes), "mmas_batch_set_launch")
+
+    def tune(self):
+        apb = C.c_int32()
+        tb = C.c_int32()
+        _check(lib.mmas_batch_tune(self._h, C.byref(apb), C.byref(tb)), "mmas_batch_tune")
+        return int(apb.value), int(tb.value)
+
+    def capture(self):
+        _check(lib.mmas_batch_capture(self._h), "mmas_batch_capture")
+
+    def step(self):
+        _check(lib.mmas_batch_step(self._h), "mmas_batch_step")
+
+    def iteration(self) -> int:
+        it = C.c_uint32()
+        _check(lib.mmas_batch_iteration(self._h, C.byref(it)), "mmas_batch_iteration")
+        return int(it.value)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def instance(self, i) -> Colony:
+        h = C.c_void_p()
+        _check(lib.mmas_batch_context(self._h, i, C.byref(h)), "mmas_batch_context")
+        p = self._params[i]
+        return _View(h, int(p.n), int(p.ants), p, self.ws, self.stream)

@@ -1,5 +1,5 @@
 """The synthetic instance recipes: deterministic, symmetric, positive off the
-diagonal (the problem statement of Sec. 2), with the stated spatial layout."""
+diagonal (the problem statement of Sec. 2.1), with the stated spatial layout."""
 import numpy as np
 
 from paper_2003_11902_amd import instances as I

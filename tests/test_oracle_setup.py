@@ -1,4 +1,4 @@
-"""Pins of the set-up steps of Alg. 1: eta = 1/d (Sec. 2), candidate lists
+"""Pins of the set-up steps of Alg. 1: eta = 1/d (Sec. 2.1), candidate lists
 (Sec. 4.3), the nearest-neighbour tour and the trail limits of Stuetzle and
 Hoos with p_best (Sec. 5)."""
 import numpy as np

@@ -1,4 +1,4 @@
-"""Pins of the oracle's 2-opt (Sec. 5.5: neighbour lists and don't-look bits,
+"""Pins of the oracle's 2-opt (Sec. 5.7: neighbour lists and don't-look bits,
 after Bentley) and an end-to-end sanity bar for the whole method."""
 import itertools
 

@@ -1,4 +1,4 @@
-"""Pins of the pheromone update of Alg. 1 (Sec. 3.1): evaporation
+"""Pins of the pheromone update of Alg. 1 (Sec. 2.1): evaporation
 tau <- max((1 - rho) tau, tau_min), deposit of 1/C_ib on the iteration best's
 edges (both directions of a symmetric instance), the tau_max clamp, and the
 global-best / limits bookkeeping."""
