@@ -232,6 +232,64 @@ mmas_status mmas_batch_context(mmas_batch* b, int32_t index, mmas_ctx** ctx);
 
 void mmas_batch_destroy(mmas_batch* b);
 
+/* ---- learned heuristic -----------------------------------------------------
+ * A project addition beside the paper's eta = 1/d (Sec. 2.1): an edge-scoring
+ * MLP (8 features -> 128 -> 128 -> 1, GELU, bfloat16 on MFMA with FP32
+ * accumulation) over the 16 nearest cities of each city, and
+ * eta_ij = (1/d_ij) * 2 sigmoid(s_ij) on those edges (1/d elsewhere), so that
+ * s = 0 is exactly the plain heuristic. Parameters are one FP32 array of
+ * mmas_mlp_param_count() floats: W1 [16][128] (rows 8..15 multiply zero
+ * inputs), b1 [128], W2 [128][128] (row = input unit), b2 [128], w3 [128],
+ * b3. Kernels read bfloat16 copies (mmas_mlp_packed_count() uint16) made by
+ * mmas_mlp_pack. All pointers are device memory; every call enqueues on
+ * `hip_stream` and returns. */
+int32_t mmas_mlp_param_count(void);
+int32_t mmas_mlp_packed_count(void);
+
+/* Features of the directed edges i -> knn[i][r] (e = 16 i + r, E = 16 n):
+ * the 16 nearest cities by (distance, index) into knn_dev (n*16 uint16), the
+ * 8 FP32 features into feat_dev (E*8, may be NULL) and the bfloat16 MLP input
+ * into x_dev (E*16, features then 8 zeros). Features, with dbar_i the mean
+ * distance of i to its 16 nearest: d_ij/dbar_i, r/15, (rank of i among the 16
+ * nearest of j, or 16)/16, (x_j-x_i)/dbar_i, (y_j-y_i)/dbar_i, indeg(j)/16,
+ * indeg(i)/16, dbar_j/dbar_i (indeg = how many cities list it). xy_dev: n*2
+ * FP32 coordinates; scratch_dev: 8n bytes. n >= 17. */
+mmas_status mmas_mlp_features(const int32_t* dist_dev, const float* xy_dev, int32_t n, void* scratch_dev,
+                              uint16_t* knn_dev, float* feat_dev, uint16_t* x_dev, void* hip_stream);
+
+/* bfloat16 working copies of the parameters. */
+mmas_status mmas_mlp_pack(const float* params_dev, uint16_t* packed_dev, void* hip_stream);
+
+/* Scores s (E floats) of E input rows. */
+mmas_status mmas_mlp_forward(const uint16_t* x_dev, int64_t edges, const float* params_dev,
+                             const uint16_t* packed_dev, float* s_dev, void* hip_stream);
+
+/* Gradient of the mean binary cross-entropy with logits against targets in
+ * [0,1] (E floats): grad_dev receives param_count floats and then the loss
+ * sum. `groups` workgroups (1..4096) each write a partial sum into
+ * partial_dev (groups * (param_count + 1) floats); they are added in a fixed
+ * order, so the result is deterministic. */
+mmas_status mmas_mlp_grad(const uint16_t* x_dev, const float* target_dev, int64_t edges, const float* params_dev,
+                          const uint16_t* packed_dev, float* partial_dev, int32_t groups, float* grad_dev,
+                          void* hip_stream);
+
+/* One Adam step (step >= 1) in FP32 on all parameters:
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * p -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps). */
+mmas_status mmas_mlp_adam(float* params_dev, const float* grad_dev, float* m_dev, float* v_dev, float lr, float beta1,
+                          float beta2, float eps, int32_t step, void* hip_stream);
+
+/* Training targets: for each kNN edge (16 i + r), the share of the `tours`
+ * tours (tours x n uint16, device) that contain the edge {i, knn[i][r]}. */
+mmas_status mmas_mlp_labels(const uint16_t* tours_dev, int32_t tours, int32_t n, const uint16_t* knn_dev,
+                            float* target_dev, void* hip_stream);
+
+/* Installs the learned heuristic in a context: eta^beta with
+ * eta_ij = fl(fl(1/d_ij) * fl(2 sigmoid(s_ij))) on the kNN edges (score_dev:
+ * n*16 floats by edge 16 i + r, knn_dev: n*16), 1/d elsewhere; sigmoid uses
+ * the library's FP32 exp. Marks choice_info stale. n >= 17. */
+mmas_status mmas_set_learned_heuristic(mmas_ctx* ctx, const uint16_t* knn_dev, const float* score_dev);
+
 /* Diagnostics, for checking the device arithmetic against an independent
  * implementation: the device FP32 logarithm of `count` values in (0,1)
  * (`dev_u` -> `dev_out`, device arrays), and the Philox draw words for

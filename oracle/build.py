@@ -9,13 +9,13 @@ LIB = os.path.join(HERE, "liboracle.so")
 # -ffp-contract=off: no fused multiply-add, every FP32 operation rounds on its own.
 # No -ffast-math and no -march=native (the library also runs on other hosts).
 CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
-          "-fopenmp", "-Wall", "-Wextra"]
+          "-fopenmp", "-Wall", "-Wextra", "-D_GNU_SOURCE"]
 
 
 def build(verbose: bool = False) -> str:
-    src = os.path.join(HERE, "mmas_oracle.c")
+    srcs = [os.path.join(HERE, f) for f in ("mmas_oracle.c", "learned_oracle.c")]
     tmp = LIB + ".tmp"
-    cmd = ["gcc", *CFLAGS, "-o", tmp, src, "-lm"]
+    cmd = ["gcc", *CFLAGS, "-o", tmp, *srcs, "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)

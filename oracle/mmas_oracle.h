@@ -137,6 +137,20 @@ int64_t orc_two_opt_tour(int n, const int32_t* dist, const uint16_t* nn, int k, 
 /* Tour length, closing edge included. */
 int64_t orc_tour_length(int n, const int32_t* dist, const uint16_t* tour);
 
+/* ---- learned heuristic (learned_oracle.c) -------------------------------- */
+
+float orc_bf16_round(float x);
+float orc_expf(float x);
+void orc_knn_features(int n, const int32_t* dist, const float* xy, uint16_t* knn, float* feat);
+void orc_mlp_forward(int64_t E, const float* X, const float* W1, const float* b1, const float* W2, const float* b2,
+                     const float* w3, float b3, int quantize, float* s_out);
+double orc_mlp_backward(int64_t E, const float* X, const float* f, const float* W1, const float* b1, const float* W2,
+                        const float* b2, const float* w3, float b3, int quantize, float* gW1, float* gb1, float* gW2,
+                        float* gb2, float* gw3, float* gb3);
+void orc_adam(int64_t count, float* p, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
+              float c1, float c2);
+void orc_install_eta(int n, const int32_t* dist, const uint16_t* knn, const float* s, int beta, float* heur);
+
 #ifdef __cplusplus
 }
 #endif

@@ -72,6 +72,17 @@ def lib():
         L.orc_two_opt_tour.restype = C.c_int64
         L.orc_tour_length.argtypes = [C.c_int, p, p]
         L.orc_tour_length.restype = C.c_int64
+        L.orc_bf16_round.argtypes = [C.c_float]
+        L.orc_bf16_round.restype = C.c_float
+        L.orc_expf.argtypes = [C.c_float]
+        L.orc_expf.restype = C.c_float
+        L.orc_knn_features.argtypes = [C.c_int, p, p, p, p]
+        L.orc_mlp_forward.argtypes = [C.c_int64, p, p, p, p, p, p, C.c_float, C.c_int, p]
+        L.orc_mlp_backward.argtypes = [C.c_int64, p, p, p, p, p, p, p, C.c_float, C.c_int, p, p, p, p, p, p]
+        L.orc_mlp_backward.restype = C.c_double
+        L.orc_adam.argtypes = [C.c_int64, p, p, p, p, C.c_float, C.c_float, C.c_float, C.c_float, C.c_float,
+                               C.c_float]
+        L.orc_install_eta.argtypes = [C.c_int, p, p, p, C.c_int, p]
         _lib = L
     return _lib
 
@@ -288,3 +299,89 @@ class Colony:
         out = np.zeros(2, dtype=np.int64)
         lib().orc_get_iteration_best(self._h, _ptr(out))
         return int(out[0]), int(out[1])
+
+
+# ---- learned heuristic ----
+HID = 128
+IN = 16
+
+
+def bf16(x) -> np.ndarray:
+    """Round float32 values to the nearest bfloat16 (ties to even), as float32."""
+    a = np.ascontiguousarray(x, dtype=np.float32)
+    b = a.view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).reshape(a.shape)
+
+
+def expf(x: float) -> np.float32:
+    return np.float32(lib().orc_expf(float(np.float32(x))))
+
+
+def knn_features(dist, xy):
+    d = np.ascontiguousarray(dist, dtype=np.int32)
+    n = d.shape[0]
+    xyf = np.ascontiguousarray(xy, dtype=np.float32)
+    knn = np.zeros((n, 16), dtype=np.uint16)
+    feat = np.zeros((n * 16, 8), dtype=np.float32)
+    lib().orc_knn_features(n, _ptr(d), _ptr(xyf), _ptr(knn), _ptr(feat))
+    return knn, feat
+
+
+def pad_inputs(feat) -> np.ndarray:
+    X = np.zeros((feat.shape[0], IN), dtype=np.float32)
+    X[:, :8] = feat
+    return X
+
+
+class MLPParams:
+    """W1 [16,128], b1 [128], W2 [128,128], b2 [128], w3 [128], b3 scalar (float32)."""
+
+    def __init__(self, W1, b1, W2, b2, w3, b3):
+        self.W1 = np.ascontiguousarray(W1, np.float32)
+        self.b1 = np.ascontiguousarray(b1, np.float32)
+        self.W2 = np.ascontiguousarray(W2, np.float32)
+        self.b2 = np.ascontiguousarray(b2, np.float32)
+        self.w3 = np.ascontiguousarray(w3, np.float32)
+        self.b3 = np.float32(np.asarray(b3, dtype=np.float32).reshape(-1)[0])
+
+    def arrays(self):
+        return self.W1, self.b1, self.W2, self.b2, self.w3
+
+
+def mlp_forward(X, P: MLPParams, quantize=True):
+    X = np.ascontiguousarray(X, np.float32)
+    s = np.zeros(X.shape[0], dtype=np.float32)
+    lib().orc_mlp_forward(X.shape[0], _ptr(X), *(_ptr(a) for a in P.arrays()), float(P.b3), int(quantize), _ptr(s))
+    return s
+
+
+def mlp_backward(X, f, P: MLPParams, quantize=True):
+    X = np.ascontiguousarray(X, np.float32)
+    f = np.ascontiguousarray(f, np.float32)
+    g = MLPParams(np.zeros_like(P.W1), np.zeros_like(P.b1), np.zeros_like(P.W2), np.zeros_like(P.b2),
+                  np.zeros_like(P.w3), 0.0)
+    gb3 = C.c_float()
+    loss = lib().orc_mlp_backward(X.shape[0], _ptr(X), _ptr(f), *(_ptr(a) for a in P.arrays()), float(P.b3),
+                                  int(quantize), *(_ptr(a) for a in g.arrays()), C.byref(gb3))
+    g.b3 = np.float32(gb3.value)
+    return float(loss), g
+
+
+def adam(p, g, m, v, lr, b1, b2, eps, t):
+    c1 = np.float32(1.0 - b1 ** t)
+    c2 = np.float32(1.0 - b2 ** t)
+    for a in (p, g, m, v):
+        assert a.dtype == np.float32 and a.flags.c_contiguous
+    lib().orc_adam(p.size, _ptr(p), _ptr(g), _ptr(m), _ptr(v), float(np.float32(lr)), float(np.float32(b1)),
+                   float(np.float32(b2)), float(np.float32(eps)), float(c1), float(c2))
+
+
+def install_eta(dist, knn, s, beta):
+    d = np.ascontiguousarray(dist, dtype=np.int32)
+    n = d.shape[0]
+    k = np.ascontiguousarray(knn, dtype=np.uint16)
+    sc = np.ascontiguousarray(s, dtype=np.float32)
+    heur = np.zeros((n, n), dtype=np.float32)
+    lib().orc_install_eta(n, _ptr(d), _ptr(k), _ptr(sc), beta, _ptr(heur))
+    return heur

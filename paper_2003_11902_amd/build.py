@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmmas.so")
-SOURCES = ["mmas.hip", "prep.hip", "construct.hip", "update.hip", "two_opt.hip", "batch.hip", "diag.hip"]
+SOURCES = ["mmas.hip", "prep.hip", "construct.hip", "update.hip", "two_opt.hip", "batch.hip", "learned.hip", "diag.hip"]
 ARCH = os.environ.get("MMAS_OFFLOAD_ARCH", "gfx950")
 
 # Bit-exact FP32: no contraction into FMA, denormals kept, IEEE division (the

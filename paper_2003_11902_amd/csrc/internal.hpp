@@ -89,6 +89,22 @@ hipError_t launch_batch_update(const BatchItem* items, int count, const int* row
                                uint32_t* it_dev, uint32_t* queue, hipStream_t st);
 int max_lds_per_block();
 
+// ---- learned heuristic (learned.hip) ----
+int mlp_param_count();
+int mlp_packed_count();
+hipError_t launch_features(const int32_t* dist, const float* xy, const uint16_t* knn, int n, float* dbar, int* indeg,
+                           float* feat, uint16_t* X, hipStream_t st);
+hipError_t launch_pack(const float* p, uint16_t* pk, hipStream_t st);
+hipError_t launch_mlp_forward(const uint16_t* X, const float* p, const uint16_t* pk, int64_t E, float* s,
+                              hipStream_t st);
+hipError_t launch_mlp_train(const uint16_t* X, const float* f, const float* p, const uint16_t* pk, int64_t E,
+                            float* partial, int groups, float* grad, hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, float lr, float b1, float b2, float eps, float c1,
+                       float c2, hipStream_t st);
+hipError_t launch_install(const int32_t* dist, const uint16_t* knn, const float* s, const uint16_t* cand, int n, int cl,
+                          int beta, int dense, float* heur, hipStream_t st);
+hipError_t launch_labels(const uint16_t* tours, int R, int n, const uint16_t* knn, float* label, hipStream_t st);
+
 // LDS bytes one ant needs in the construction kernel (0 if it cannot run).
 size_t construct_lds_per_ant(const Shape& s);
 // LDS bytes of the 2-opt kernel (one tour per workgroup).

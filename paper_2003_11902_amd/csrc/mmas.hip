@@ -294,6 +294,16 @@ mmas_status mmas_set_pheromone(mmas_ctx* c, const float* host_src) {
     return MMAS_OK;
 }
 
+mmas_status mmas_set_learned_heuristic(mmas_ctx* c, const uint16_t* knn_dev, const float* score_dev) {
+    if (!c || !knn_dev || !score_dev || c->s.n < 17) return MMAS_EINVAL;
+    const Shape& s = c->s;
+    hipError_t e = mmas::launch_install(c->v.dist, knn_dev, score_dev, c->v.cand, s.n, s.cl, s.beta,
+                                        s.pher == MMAS_PHER_DENSE ? 1 : 0, c->v.heur, c->stream);
+    if (e != hipSuccess) return MMAS_EHIP;
+    c->choice_stale = true;
+    return MMAS_OK;
+}
+
 mmas_status mmas_synchronize(mmas_ctx* c) {
     if (!c) return MMAS_EINVAL;
     return hip_status(hipStreamSynchronize(c->stream));

@@ -53,7 +53,9 @@ EXPORTED = (
     "mmas_eval_log", "mmas_eval_draws", "mmas_set_launch",
     "mmas_batch_workspace_bytes", "mmas_batch_create", "mmas_batch_set_launch", "mmas_batch_tune",
     "mmas_batch_capture", "mmas_batch_step", "mmas_batch_iteration", "mmas_batch_context",
-    "mmas_batch_destroy",
+    "mmas_batch_destroy", "mmas_mlp_param_count", "mmas_mlp_packed_count", "mmas_mlp_features",
+    "mmas_mlp_pack", "mmas_mlp_forward", "mmas_mlp_grad", "mmas_mlp_adam", "mmas_mlp_labels",
+    "mmas_set_learned_heuristic",
 )
 
 
@@ -129,6 +131,24 @@ def _load():
     L.mmas_batch_context.restype = C.c_int
     L.mmas_batch_destroy.argtypes = [p]
     L.mmas_batch_destroy.restype = None
+    L.mmas_mlp_param_count.argtypes = []
+    L.mmas_mlp_param_count.restype = C.c_int32
+    L.mmas_mlp_packed_count.argtypes = []
+    L.mmas_mlp_packed_count.restype = C.c_int32
+    L.mmas_mlp_features.argtypes = [p, p, C.c_int32, p, p, p, p, p]
+    L.mmas_mlp_features.restype = C.c_int
+    L.mmas_mlp_pack.argtypes = [p, p, p]
+    L.mmas_mlp_pack.restype = C.c_int
+    L.mmas_mlp_forward.argtypes = [p, C.c_int64, p, p, p, p]
+    L.mmas_mlp_forward.restype = C.c_int
+    L.mmas_mlp_grad.argtypes = [p, p, C.c_int64, p, p, p, C.c_int32, p, p]
+    L.mmas_mlp_grad.restype = C.c_int
+    L.mmas_mlp_adam.argtypes = [p, p, p, p, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32, p]
+    L.mmas_mlp_adam.restype = C.c_int
+    L.mmas_mlp_labels.argtypes = [p, C.c_int32, C.c_int32, p, p, p]
+    L.mmas_mlp_labels.restype = C.c_int
+    L.mmas_set_learned_heuristic.argtypes = [p, p, p]
+    L.mmas_set_learned_heuristic.restype = C.c_int
     L.mmas_status_str.argtypes = [C.c_int]
     L.mmas_status_str.restype = C.c_char_p
     return L
@@ -273,7 +293,9 @@ class Colony:
         if nbytes == 0:
             return None
         off = ptr - self.ws.data_ptr()
-        tdt = {np.int32: torch.int32, np.float32: torch.float32, np.uint16: torch.uint16,
+        # 16-bit city ids travel as int16 tensors (same bits; torch's uint16
+        # supports few operations)
+        tdt = {np.int32: torch.int32, np.float32: torch.float32, np.uint16: torch.int16,
                np.int64: torch.int64}[_DTYPES[which]]
         return self.ws[off:off + nbytes].view(tdt)
 
@@ -286,6 +308,10 @@ class Colony:
         out = np.empty(nbytes // np.dtype(_DTYPES[which]).itemsize, dtype=_DTYPES[which])
         _check(lib.mmas_read(self._ctx, which, out.ctypes.data_as(C.c_void_p), nbytes), "mmas_read")
         return out
+
+    def set_learned_heuristic(self, knn, scores):
+        """Install eta = (1/d) 2 sigmoid(s) on the kNN edges (torch tensors on the device)."""
+        _check(lib.mmas_set_learned_heuristic(self._ctx, _dptr(knn), _dptr(scores)), "mmas_set_learned_heuristic")
 
     def set_pheromone(self, tau):
         t = np.ascontiguousarray(tau, dtype=np.float32).reshape(-1)
@@ -403,3 +429,86 @@ class Batch:
         _check(lib.mmas_batch_context(self._h, i, C.byref(h)), "mmas_batch_context")
         p = self._params[i]
         return _View(h, int(p.n), int(p.ants), p, self.ws, self.stream)
+
+
+# ---- learned heuristic: thin wrappers over mmas_mlp_* (torch device tensors) ----
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _cur_stream():
+    import torch
+
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def mlp_param_count() -> int:
+    return int(lib.mmas_mlp_param_count())
+
+
+def mlp_packed_count() -> int:
+    return int(lib.mmas_mlp_packed_count())
+
+
+def mmas_mlp_features(dist, xy, with_features=False):
+    """(knn [n,16], X [16n,16] bfloat16 bits, feat float32 [16n,8] or None); 16-bit
+    arrays are int16 tensors holding the unsigned bits."""
+    import torch
+
+    n = int(dist.shape[0])
+    dev = dist.device
+    knn = torch.empty((n, 16), dtype=torch.int16, device=dev)
+    X = torch.empty((16 * n, 16), dtype=torch.int16, device=dev)
+    feat = torch.empty((16 * n, 8), dtype=torch.float32, device=dev) if with_features else None
+    scratch = torch.empty(8 * n, dtype=torch.uint8, device=dev)
+    _check(lib.mmas_mlp_features(_dptr(dist), _dptr(xy), n, _dptr(scratch), _dptr(knn), _dptr(feat), _dptr(X),
+                                 _cur_stream()), "mmas_mlp_features")
+    return knn, X, feat
+
+
+def mmas_mlp_pack(params):
+    import torch
+
+    pk = torch.empty(mlp_packed_count(), dtype=torch.int16, device=params.device)
+    _check(lib.mmas_mlp_pack(_dptr(params), _dptr(pk), _cur_stream()), "mmas_mlp_pack")
+    return pk
+
+
+def mmas_mlp_forward(X, params, packed):
+    import torch
+
+    E = int(X.shape[0])
+    s = torch.empty(E, dtype=torch.float32, device=X.device)
+    _check(lib.mmas_mlp_forward(_dptr(X), E, _dptr(params), _dptr(packed), _dptr(s), _cur_stream()),
+           "mmas_mlp_forward")
+    return s
+
+
+def mmas_mlp_grad(X, target, params, packed, groups=256, partial=None, grad=None):
+    """Gradient (param_count floats) and the loss sum (last element)."""
+    import torch
+
+    E = int(X.shape[0])
+    P = mlp_param_count()
+    if partial is None:
+        partial = torch.empty(groups * (P + 1), dtype=torch.float32, device=X.device)
+    if grad is None:
+        grad = torch.empty(P + 1, dtype=torch.float32, device=X.device)
+    _check(lib.mmas_mlp_grad(_dptr(X), _dptr(target), E, _dptr(params), _dptr(packed), _dptr(partial), groups,
+                             _dptr(grad), _cur_stream()), "mmas_mlp_grad")
+    return grad
+
+
+def mmas_mlp_adam(params, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib.mmas_mlp_adam(_dptr(params), _dptr(grad), _dptr(m), _dptr(v), lr, beta1, beta2, eps, step,
+                             _cur_stream()), "mmas_mlp_adam")
+
+
+def mmas_mlp_labels(tours, knn):
+    import torch
+
+    R, n = int(tours.shape[0]), int(tours.shape[1])
+    out = torch.empty((n, 16), dtype=torch.float32, device=tours.device)
+    _check(lib.mmas_mlp_labels(_dptr(tours), R, n, _dptr(knn), _dptr(out), _cur_stream()), "mmas_mlp_labels")
+    return out
