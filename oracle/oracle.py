@@ -369,8 +369,9 @@ def mlp_backward(X, f, P: MLPParams, quantize=True):
 
 
 def adam(p, g, m, v, lr, b1, b2, eps, t):
-    c1 = np.float32(1.0 - b1 ** t)
-    c2 = np.float32(1.0 - b2 ** t)
+    # bias corrections 1 - beta^t from the FP32 betas, raised in float64
+    c1 = np.float32(1.0 - math.pow(float(np.float32(b1)), t))
+    c2 = np.float32(1.0 - math.pow(float(np.float32(b2)), t))
     for a in (p, g, m, v):
         assert a.dtype == np.float32 and a.flags.c_contiguous
     lib().orc_adam(p.size, _ptr(p), _ptr(g), _ptr(m), _ptr(v), float(np.float32(lr)), float(np.float32(b1)),

@@ -46,6 +46,8 @@ struct mmas_batch {
 namespace {
 
 constexpr size_t kAlign = 256;
+// LDS the persistent construction kernel declares statically (its tile index)
+constexpr int kStaticLds = 64;
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Header {
@@ -191,7 +193,7 @@ mmas_status mmas_batch_create(int32_t count, const int32_t* const* dists_host, c
         return MMAS_EHIP;
     }
     b->ants_per_block = 4;
-    b->table_bytes = std::max(0, mmas::max_lds_per_block() - b->ants_per_block * b->per_ant);
+    b->table_bytes = std::max(0, (mmas::max_lds_per_block() - kStaticLds - b->ants_per_block * b->per_ant) & ~15);
     r = rebuild_tiles(b);
     if (r != MMAS_OK) {
         for (mmas_ctx* c : b->ctx) mmas_destroy(c);
@@ -207,7 +209,7 @@ mmas_status mmas_batch_set_launch(mmas_batch* b, int32_t ants_per_block, int32_t
     if (ants_per_block != 1 && ants_per_block != 2 && ants_per_block != 4 && ants_per_block != 8 &&
         ants_per_block != 16)
         return MMAS_EINVAL;
-    const int budget = mmas::max_lds_per_block() - ants_per_block * b->per_ant;
+    const int budget = (mmas::max_lds_per_block() - kStaticLds - ants_per_block * b->per_ant) & ~15;
     if (budget < 0) return MMAS_EUNSUPPORTED;
     if (table_bytes < -1) return MMAS_EINVAL;
     drop_graph(b);
@@ -223,7 +225,7 @@ mmas_status mmas_batch_tune(mmas_batch* b, int32_t* ants_per_block, int32_t* tab
     };
     std::vector<Cand> cands;
     for (int apb : {4, 8, 16}) {
-        const int budget = mmas::max_lds_per_block() - apb * b->per_ant;
+        const int budget = mmas::max_lds_per_block() - kStaticLds - apb * b->per_ant;
         if (budget < 0) continue;
         cands.push_back({apb, -1});
         cands.push_back({apb, 0});

@@ -19,6 +19,13 @@ namespace mmas {
 namespace {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
+
+// pointers typed with their address space, so that an LDS read and a global
+// read of the same element are never folded into one generic (flat) load
+template <class T>
+using LdsPtr = __attribute__((address_space(3))) T*;
+template <class T>
+using GlbPtr = __attribute__((address_space(1))) T*;
 constexpr size_t kDrawBytes = 4 * kWave * sizeof(float);  // candidate draws of the next steps
 
 // ---- tabu variants ---------------------------------------------------------
@@ -197,6 +204,11 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
 
     float tmin_a = 0.0f;
     if (kPher == MMAS_PHER_CANDIDATES) tmin_a = powi(vw.state->tau_min, s.alpha);
+    // (C-style casts: the only casts that change the address space)
+    const LdsPtr<const uint16_t> lds_cand = (LdsPtr<const uint16_t>)tcand;
+    const LdsPtr<const float> lds_chc = (LdsPtr<const float>)tchc;
+    const GlbPtr<const uint16_t> glb_cand = (GlbPtr<const uint16_t>)vw.cand;
+    const GlbPtr<const float> glb_chc = (GlbPtr<const float>)vw.chc;
 
     // start city: floor(x * n / 2^32) of draw (step 0, slot 0)
     const uint32_t x0 = draw_block(seed, it, (uint32_t)ant, 0u, 0u).w[0];
@@ -223,17 +235,19 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
         uint32_t next = kNone;
         if (cl > 0) {
             // candidate phase: lane r holds rank r of cur's list
-            uint32_t node = 0u;  // lanes past the list look at city 0 and get no key
-            float w = 0.0f;
-            if (lane < cl) {
-                const int e = (int)cur * cl + lane;
-                if ((int)cur < R) {
-                    node = tcand[e];
-                    w = tchc[e];
-                } else {
-                    node = vw.cand[e];
-                    w = vw.chc[e];
-                }
+            // every lane loads a valid entry (lanes past the list repeat the
+            // last one and get no key); the row comes from LDS or from global
+            // memory through separate, address-space-typed loads
+            uint32_t node;
+            float w;
+            const int cs = __builtin_amdgcn_readfirstlane((int)cur);
+            const int e = cs * cl + (lane < cl ? lane : cl - 1);
+            if (cs < R) {
+                node = lds_cand[e];
+                w = lds_chc[e];
+            } else {
+                node = glb_cand[e];
+                w = glb_chc[e];
             }
             const int j = (k - 1) & (S - 1);
             if (j == 0) {
@@ -453,11 +467,15 @@ int batch_construct_grid(int tabu, int pher, int ants_per_block, int lds_bytes) 
         kern = pher == MMAS_PHER_DENSE ? (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_DENSE>
                                        : (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_CANDIDATES>;
     if (lds_bytes > 64 * 1024 &&
-        hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes) != hipSuccess)
+        hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes) != hipSuccess) {
+        (void)hipGetLastError();  // do not leave the error for the next launch check
         return 0;
+    }
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * ants_per_block, lds_bytes) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * ants_per_block, lds_bytes) != hipSuccess) {
+        (void)hipGetLastError();
         return 0;
+    }
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
