@@ -58,6 +58,60 @@ def cpu_baseline(dist, w, seed, budget_s):
                       f"workload, OpenMP over ants, {el:.1f} s"}
 
 
+def run_batched(args):
+    """Many instances per step (mmas_batch_*): autotuned launch shape, one
+    captured graph per step."""
+    import torch
+
+    from paper_2003_11902_amd import instances as I
+    from paper_2003_11902_amd import mmas as M
+
+    t0 = time.perf_counter()
+    insts = I.batch_instances(args.batch_count)
+    dists = [d for _, d in insts]
+    params = [M.make_params(d.shape[0], d.shape[0], cand_len=32, rho=0.02, seed=1 + k, tabu=args.tabu)
+              for k, d in enumerate(dists)]
+    b = M.Batch(dists, params)
+    setup_s = time.perf_counter() - t0
+    apb, tb = b.tune()
+    if not args.no_graph:
+        b.capture()
+    for _ in range(args.warmup):
+        b.step()
+    b.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        b.step()
+    b.synchronize()
+    elapsed = time.perf_counter() - t1
+    print(f"[bench] batched: set-up {setup_s:.1f} s, {args.steps} steps in {elapsed:.3f} s", file=sys.stderr,
+          flush=True)
+    total_ants = sum(int(p.ants) for p in params)
+    # algorithmic bytes of one construction step over all instances, with the
+    # fallback enumeration counts of the last step
+    nbytes = 0.0
+    for k, (d, p) in enumerate(zip(dists, params)):
+        n = d.shape[0]
+        fb = b.instance(k).fallback()[1].sum()
+        nbytes += algorithmic_bytes(n, min(32, n - 1), int(p.ants), float(fb))
+    ms = elapsed / args.steps * 1e3
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    out = {
+        "metric": "tours constructed/sec, batched instances (1 GPU)",
+        "value": total_ants * args.steps / elapsed, "unit": "tours/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batched{args.batch_count}", "instances": args.batch_count,
+                   "n_range": [100, 2000], "ants": "n per instance", "cand_len": 32, "rho": 0.02,
+                   "tabu": args.tabu, "graph": not args.no_graph, "ants_per_block": apb, "table_bytes": tb,
+                   "total_ants": total_ants},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "whole step (construction + update)", "bytes_per_step": nbytes},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +125,11 @@ def main():
     ap.add_argument("--table-rows", type=int, default=-1)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--batched", action="store_true",
+                    help="time the batched workload (256 instances, n in [100, 2000], ants = n) "
+                         "instead of the single colony")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times) and exit; "
                          "its FETCH_SIZE / WRITE_SIZE calibrate the HBM traffic counters")
@@ -94,6 +153,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration_copy_bytes": src.numel() * 4}), flush=True)
         return
+    if args.batched:
+        return run_batched(args)
     xy, dist, w = I.workload_instance(args.workload)
     if args.ants:
         w["ants"] = args.ants

@@ -27,6 +27,7 @@ using LdsPtr = __attribute__((address_space(3))) T*;
 template <class T>
 using GlbPtr = __attribute__((address_space(1))) T*;
 constexpr size_t kDrawBytes = 4 * kWave * sizeof(float);  // candidate draws of the next steps
+constexpr size_t kScratchBytes = 16;                       // per-ant counter of the fallback list
 
 // ---- tabu variants ---------------------------------------------------------
 
@@ -109,10 +110,12 @@ __device__ __forceinline__ void keep_best(uint32_t code, uint32_t node, uint32_t
 }
 
 // The unvisited cities of a bitmask tabu, gathered into `list` (LDS, one
-// 16-bit entry per city; any order). Returns their number.
-__device__ int gather_unvisited(const BitmaskTabu& tabu, int n, uint16_t* list, int lane) {
+// 16-bit entry per city). Lanes claim their slots with an LDS atomic add, so
+// the order of the list varies; the fallback's result does not depend on it
+// (largest key, lowest city on ties). Returns their number.
+__device__ int gather_unvisited(const BitmaskTabu& tabu, int n, uint16_t* list, uint32_t* counter, int lane) {
     const int words = (n + 31) >> 5;
-    int total = 0;
+    if (lane == 0) *counter = 0u;
     for (int w0 = 0; w0 < words; w0 += kWave) {
         const int wi = w0 + lane;
         uint32_t fr = 0u;
@@ -120,21 +123,16 @@ __device__ int gather_unvisited(const BitmaskTabu& tabu, int n, uint16_t* list, 
             fr = ~tabu.bits[wi];
             if (wi == words - 1 && (n & 31)) fr &= (1u << (n & 31)) - 1u;
         }
-        const int c = __popc(fr);
-        int inc = c;  // inclusive prefix sum of the counts over the wave
-        for (int o = 1; o < kWave; o <<= 1) {
-            const int y = __shfl_up(inc, o);
-            if (lane >= o) inc += y;
+        if (fr) {
+            int p = (int)atomicAdd(counter, (uint32_t)__popc(fr));
+            while (fr) {
+                const int b = __ffs(fr) - 1;
+                fr &= fr - 1u;
+                list[p++] = (uint16_t)(wi * 32 + b);
+            }
         }
-        int p = total + inc - c;
-        while (fr) {
-            const int b = __ffs(fr) - 1;
-            fr &= fr - 1u;
-            list[p++] = (uint16_t)(wi * 32 + b);
-        }
-        total += __shfl(inc, kWave - 1);
     }
-    return total;
+    return (int)*counter;
 }
 
 // All-node fallback over a list of the L unvisited cities: city v draws slot
@@ -199,8 +197,8 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
     // per-ant LDS: the draws of the next steps (256 floats), then the tabu
     float* lnbuf = reinterpret_cast<float*>(region);
     typename TabuOf<kTabu>::type tabu;
-    tabu.init(region + kDrawBytes, n, lane);
-    uint16_t* ulist = reinterpret_cast<uint16_t*>(region + kDrawBytes + align16(4 * ((n + 31) / 32)));
+    tabu.init(region + kDrawBytes + kScratchBytes, n, lane);
+    uint16_t* ulist = reinterpret_cast<uint16_t*>(region + kDrawBytes + kScratchBytes + align16(4 * ((n + 31) / 32)));
 
     float tmin_a = 0.0f;
     if (kPher == MMAS_PHER_CANDIDATES) tmin_a = powi(vw.state->tau_min, s.alpha);
@@ -277,7 +275,7 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
             const uint16_t* list;
             int L;
             if constexpr (kTabu == MMAS_TABU_BITMASK) {
-                L = gather_unvisited(tabu, n, ulist, lane);
+                L = gather_unvisited(tabu, n, ulist, reinterpret_cast<uint32_t*>(region + kDrawBytes), lane);
                 list = ulist;
             } else {
                 L = tabu.L;
@@ -437,7 +435,7 @@ size_t construct_lds_per_ant(const Shape& s) {
     // list of unvisited cities built in a fallback
     const int bits = align16(4 * ((s.n + 31) / 32));
     const int list = align16(2 * s.n);
-    return kDrawBytes + (s.tabu == MMAS_TABU_BITMASK ? bits + list : list);
+    return kDrawBytes + kScratchBytes + (s.tabu == MMAS_TABU_BITMASK ? bits + list : list);
 }
 
 hipError_t launch_batch_construct(const BatchItem* items, const BatchTile* tiles, int ntiles, uint32_t* queue,
