@@ -27,6 +27,31 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "traffic_clustered1002.json")
+
+
+def construct_source_sha256() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in ("construct.hip", "device.hpp"):
+        with open(os.path.join(ROOT, "paper_2003_11902_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per construction launch from the committed counter record, or
+    None when there is none for this workload or the kernel source changed
+    since the counters were taken."""
+    try:
+        with open(TRAFFIC_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("workload") != workload or rec.get("source_sha256") != construct_source_sha256():
+        return None
+    return rec.get("construct_hbm_bytes")
 
 
 def algorithmic_bytes(n: int, cl: int, ants: int, fallback_nodes: float) -> float:
@@ -220,7 +245,8 @@ def main():
                    "pheromone": w["pher"], "instance": f"{w['kind']} seed {w['seed']}",
                    "ants_per_block": args.ants_per_block or 4, "table_rows": args.table_rows},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(args.workload) if args.tabu == "bitmask" else None,
                      "kernel": "k_construct", "kernel_ms": cons_ms,
                      "bytes_per_launch": nbytes},
     }
