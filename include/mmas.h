@@ -300,6 +300,10 @@ mmas_status mmas_eval_draws(uint64_t seed, const uint32_t* dev_it, const uint32_
                             const uint32_t* dev_step, const uint32_t* dev_slot, uint32_t* dev_out,
                             size_t count, void* hip_stream);
 
+/* Text of the HIP error behind the calling thread's last MMAS_EHIP (which
+ * step failed and HIP's message); "" if none. */
+const char* mmas_last_error(void);
+
 /* Static text for a status. */
 const char* mmas_status_str(mmas_status s);
 

@@ -80,10 +80,10 @@ mmas_status rebuild_tiles(mmas_batch* b) {
         for (int a0 = 0; a0 < ants; a0 += b->ants_per_block) b->tiles.push_back(mmas::BatchTile{i, a0});
     }
     b->ntiles = (int)b->tiles.size();
-    if (hipMemcpyAsync(b->d_tiles, b->tiles.data(), sizeof(mmas::BatchTile) * b->tiles.size(), hipMemcpyHostToDevice,
-                       b->stream) != hipSuccess ||
-        hipStreamSynchronize(b->stream) != hipSuccess)
-        return MMAS_EHIP;
+    hipError_t e = hipMemcpyAsync(b->d_tiles, b->tiles.data(), sizeof(mmas::BatchTile) * b->tiles.size(),
+                                  hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return mmas::hip_fail(e, "tile table");
     const int lds = b->table_bytes + b->ants_per_block * b->per_ant;
     int g = mmas::batch_construct_grid(b->tabu, b->pher, b->ants_per_block, lds);
     if (g <= 0) return MMAS_EUNSUPPORTED;
@@ -95,9 +95,9 @@ mmas_status launch_step(mmas_batch* b) {
     hipError_t e = mmas::launch_batch_construct(b->d_items, b->d_tiles, b->ntiles, b->d_queue, b->d_it, b->tabu,
                                                 b->pher, b->ants_per_block, b->table_bytes, b->per_ant, b->grid,
                                                 b->stream);
-    if (e != hipSuccess) return MMAS_EHIP;
+    if (e != hipSuccess) return mmas::hip_fail(e, "batched construction launch");
     e = mmas::launch_batch_update(b->d_items, b->count, b->d_row_start, b->total_rows, b->d_it, b->d_queue, b->stream);
-    return e == hipSuccess ? MMAS_OK : MMAS_EHIP;
+    return e == hipSuccess ? MMAS_OK : mmas::hip_fail(e, "batched update launch");
 }
 
 void drop_graph(mmas_batch* b) {
@@ -190,7 +190,7 @@ mmas_status mmas_batch_create(int32_t count, const int32_t* const* dists_host, c
     if (e != hipSuccess) {
         for (mmas_ctx* c : b->ctx) mmas_destroy(c);
         delete b;
-        return MMAS_EHIP;
+        return mmas::hip_fail(e, "batch tables");
     }
     b->ants_per_block = 4;
     b->table_bytes = std::max(0, (mmas::max_lds_per_block() - kStaticLds - b->ants_per_block * b->per_ant) & ~15);
@@ -231,7 +231,9 @@ mmas_status mmas_batch_tune(mmas_batch* b, int32_t* ants_per_block, int32_t* tab
         cands.push_back({apb, 0});
     }
     hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return MMAS_EHIP;
+    hipError_t ee = hipEventCreate(&e0);
+    if (ee == hipSuccess) ee = hipEventCreate(&e1);
+    if (ee != hipSuccess) return mmas::hip_fail(ee, "tuner events");
     float best_ms = 1e30f;
     Cand best = cands.empty() ? Cand{4, -1} : cands[0];
     mmas_status r = MMAS_OK;
@@ -243,12 +245,12 @@ mmas_status mmas_batch_tune(mmas_batch* b, int32_t* ants_per_block, int32_t* tab
         for (int rep = 0; rep < 2 && r == MMAS_OK; ++rep) {
             k_reset_queue<<<1, 64, 0, b->stream>>>(b->d_queue);
             (void)hipEventRecord(e0, b->stream);
-            if (mmas::launch_batch_construct(b->d_items, b->d_tiles, b->ntiles, b->d_queue, b->d_it, b->tabu, b->pher,
-                                             b->ants_per_block, b->table_bytes, b->per_ant, b->grid,
-                                             b->stream) != hipSuccess)
-                r = MMAS_EHIP;
+            ee = mmas::launch_batch_construct(b->d_items, b->d_tiles, b->ntiles, b->d_queue, b->d_it, b->tabu, b->pher,
+                                              b->ants_per_block, b->table_bytes, b->per_ant, b->grid, b->stream);
+            if (ee != hipSuccess) r = mmas::hip_fail(ee, "tuner launch");
             (void)hipEventRecord(e1, b->stream);
-            if (hipEventSynchronize(e1) != hipSuccess) r = MMAS_EHIP;
+            ee = hipEventSynchronize(e1);
+            if (ee != hipSuccess) r = mmas::hip_fail(ee, "tuner synchronisation");
             (void)hipEventElapsedTime(&ms, e0, e1);  // the second repetition counts
         }
         if (r == MMAS_OK && ms < best_ms) {
@@ -264,32 +266,38 @@ mmas_status mmas_batch_tune(mmas_batch* b, int32_t* ants_per_block, int32_t* tab
     if (r != MMAS_OK) return r;
     if (ants_per_block) *ants_per_block = b->ants_per_block;
     if (table_bytes) *table_bytes = b->table_bytes;
-    return hipStreamSynchronize(b->stream) == hipSuccess ? MMAS_OK : MMAS_EHIP;
+    ee = hipStreamSynchronize(b->stream);
+    return ee == hipSuccess ? MMAS_OK : mmas::hip_fail(ee, "tuner synchronisation");
 }
 
 mmas_status mmas_batch_capture(mmas_batch* b) {
     if (!b) return MMAS_EINVAL;
     if (b->stream == nullptr) return MMAS_EUNSUPPORTED;  // the null stream cannot be captured
     drop_graph(b);
-    if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return MMAS_EHIP;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return mmas::hip_fail(e, "capture begin");
     mmas_status r = launch_step(b);
     hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(b->stream, &g);
+    e = hipStreamEndCapture(b->stream, &g);
     if (r != MMAS_OK || e != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
-        return MMAS_EHIP;
+        return r != MMAS_OK ? r : mmas::hip_fail(e, "capture end");
     }
     b->graph = g;
-    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
         drop_graph(b);
-        return MMAS_EHIP;
+        return mmas::hip_fail(e, "graph instantiation");
     }
     return MMAS_OK;
 }
 
 mmas_status mmas_batch_step(mmas_batch* b) {
     if (!b) return MMAS_EINVAL;
-    if (b->exec) return hipGraphLaunch(b->exec, b->stream) == hipSuccess ? MMAS_OK : MMAS_EHIP;
+    if (b->exec) {
+        const hipError_t e = hipGraphLaunch(b->exec, b->stream);
+        return e == hipSuccess ? MMAS_OK : mmas::hip_fail(e, "graph launch");
+    }
     return launch_step(b);
 }
 
@@ -297,7 +305,7 @@ mmas_status mmas_batch_iteration(mmas_batch* b, uint32_t* iteration) {
     if (!b || !iteration) return MMAS_EINVAL;
     hipError_t e = hipMemcpyAsync(iteration, b->d_it, sizeof(uint32_t), hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    return e == hipSuccess ? MMAS_OK : MMAS_EHIP;
+    return e == hipSuccess ? MMAS_OK : mmas::hip_fail(e, "iteration read");
 }
 
 mmas_status mmas_batch_context(mmas_batch* b, int32_t index, mmas_ctx** ctx) {

@@ -59,6 +59,10 @@ struct BatchTile {
     int ant0;
 };
 
+// Records the HIP error behind an MMAS_EHIP (per thread) and returns
+// MMAS_EHIP; mmas_last_error() reads it back.
+mmas_status hip_fail(hipError_t e, const char* where);
+
 // ---- set-up (prep.hip) ----
 hipError_t launch_validate(const Views& v, const Shape& s, hipStream_t st);
 hipError_t launch_heuristic(const Views& v, const Shape& s, hipStream_t st);

@@ -554,7 +554,7 @@ hipError_t launch_labels(const uint16_t* tours, int R, int n, const uint16_t* kn
 
 namespace {
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
-mmas_status st_of(hipError_t e) { return e == hipSuccess ? MMAS_OK : MMAS_EHIP; }
+mmas_status st_of(hipError_t e) { return e == hipSuccess ? MMAS_OK : mmas::hip_fail(e, "learned-heuristic kernel"); }
 }  // namespace
 
 extern "C" {
@@ -567,7 +567,7 @@ mmas_status mmas_mlp_features(const int32_t* dist_dev, const float* xy_dev, int3
     if (!dist_dev || !xy_dev || !scratch_dev || !knn_dev || !x_dev || n < 17 || n > 65535) return MMAS_EINVAL;
     hipStream_t st = as_stream(hip_stream);
     hipError_t e = mmas::launch_nearest(dist_dev, n, 16, knn_dev, st);
-    if (e != hipSuccess) return MMAS_EHIP;
+    if (e != hipSuccess) return st_of(e);
     float* dbar = reinterpret_cast<float*>(scratch_dev);
     int* indeg = reinterpret_cast<int*>(dbar + n);
     return st_of(mmas::launch_features(dist_dev, xy_dev, knn_dev, n, dbar, indeg, feat_dev, x_dev, st));

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -103,11 +104,18 @@ T* at(char* base, size_t off, size_t len) {
     return len ? reinterpret_cast<T*>(base + off) : nullptr;
 }
 
-mmas_status hip_status(hipError_t e) { return e == hipSuccess ? MMAS_OK : MMAS_EHIP; }
+thread_local char g_last_error[256] = "";
+
+mmas_status hip_status(hipError_t e) { return e == hipSuccess ? MMAS_OK : mmas::hip_fail(e, "HIP call"); }
 
 }  // namespace
 
 namespace mmas {
+mmas_status hip_fail(hipError_t e, const char* where) {
+    snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", where, hipGetErrorString(e), (int)e);
+    return MMAS_EHIP;
+}
+
 // The device views and constants of a context (for batches).
 bool ctx_views(mmas_ctx* c, Views* v, Shape* s) {
     if (!c) return false;
@@ -147,10 +155,11 @@ mmas_status mmas_create(const int32_t* dist_host, const mmas_params* p, void* de
     }
     if (s.tabu == MMAS_TABU_COMPACT || s.tabu == MMAS_TABU_BITMASK) {
         int dev = 0, maxlds = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e != hipSuccess) {
             delete c;
-            return MMAS_EHIP;
+            return mmas::hip_fail(e, "device query");
         }
         if (mmas::construct_lds_per_ant(s) > (size_t)maxlds ||
             (s.ls_nn > 0 && mmas::two_opt_lds_bytes(s) > (size_t)maxlds)) {
@@ -177,22 +186,23 @@ mmas_status mmas_create(const int32_t* dist_host, const mmas_params* p, void* de
     v.pred = reinterpret_cast<uint16_t*>(b + c->off_pred);
 
     hipStream_t st = c->stream;
+    const char* step = "copy of the distance matrix";
     hipError_t e = hipMemcpyAsync(v.dist, dist_host, c->len[MMAS_BUF_DIST], hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemsetAsync(v.state, 0, sizeof(mmas_device_state), st);
-    if (e == hipSuccess) e = mmas::launch_validate(v, s, st);
-    if (e == hipSuccess) e = mmas::launch_nearest(v.dist, s.n, s.cl, v.cand, st);
-    if (e == hipSuccess) e = mmas::launch_nearest(v.dist, s.n, s.ls_nn, v.lsnn, st);
-    if (e == hipSuccess) e = mmas::launch_heuristic(v, s, st);
-    if (e == hipSuccess)
+    if (e == hipSuccess && (step = "state reset")) e = hipMemsetAsync(v.state, 0, sizeof(mmas_device_state), st);
+    if (e == hipSuccess && (step = "validation")) e = mmas::launch_validate(v, s, st);
+    if (e == hipSuccess && (step = "candidate lists")) e = mmas::launch_nearest(v.dist, s.n, s.cl, v.cand, st);
+    if (e == hipSuccess && (step = "2-opt lists")) e = mmas::launch_nearest(v.dist, s.n, s.ls_nn, v.lsnn, st);
+    if (e == hipSuccess && (step = "heuristic")) e = mmas::launch_heuristic(v, s, st);
+    if (e == hipSuccess && (step = "2-opt list distances"))
         e = mmas::launch_two_opt_prepare(v, s, reinterpret_cast<int32_t*>(c->ws + c->off_nnd), st);
-    if (e == hipSuccess) e = mmas::launch_nn_tour(v, s, st);
-    if (e == hipSuccess) e = mmas::launch_init_trails(v, s, st);
+    if (e == hipSuccess && (step = "nearest-neighbour tour")) e = mmas::launch_nn_tour(v, s, st);
+    if (e == hipSuccess && (step = "trail limits")) e = mmas::launch_init_trails(v, s, st);
     mmas_device_state hs;
-    if (e == hipSuccess) e = hipMemcpyAsync(&hs, v.state, sizeof(hs), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess && (step = "state read")) e = hipMemcpyAsync(&hs, v.state, sizeof(hs), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && (step = "set-up synchronisation")) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
         delete c;
-        return MMAS_EHIP;
+        return mmas::hip_fail(e, step);
     }
     if (hs.flags != 0u || !std::isfinite(hs.tau_max) || !(hs.tau_min > 0.0f)) {
         delete c;
@@ -208,7 +218,7 @@ mmas_status mmas_prepare_choice_info(mmas_ctx* c) {
     if (!c) return MMAS_EINVAL;
     if (!c->choice_stale) return MMAS_OK;
     hipError_t e = mmas::launch_choice(c->v, c->s, c->stream);
-    if (e != hipSuccess) return MMAS_EHIP;
+    if (e != hipSuccess) return hip_status(e);
     c->choice_stale = false;
     return MMAS_OK;
 }
@@ -218,7 +228,7 @@ mmas_status mmas_construct(mmas_ctx* c, uint32_t iteration) {
     mmas_status r = mmas_prepare_choice_info(c);
     if (r != MMAS_OK) return r;
     hipError_t e = mmas::launch_construct(c->v, c->s, iteration, c->stream);
-    if (e != hipSuccess) return MMAS_EHIP;
+    if (e != hipSuccess) return hip_status(e);
     c->constructed = true;
     return MMAS_OK;
 }
@@ -246,7 +256,7 @@ mmas_status mmas_update_pheromone(mmas_ctx* c) {
     if (!c) return MMAS_EINVAL;
     if (!c->constructed) return MMAS_ESTATE;
     hipError_t e = mmas::launch_update(c->v, c->s, c->stream);
-    if (e != hipSuccess) return MMAS_EHIP;
+    if (e != hipSuccess) return hip_status(e);
     c->choice_stale = false;  // refreshed by the fused pass
     return MMAS_OK;
 }
@@ -259,7 +269,7 @@ mmas_status mmas_best(mmas_ctx* c, int32_t* tour_host, int64_t* len_host) {
     if (e == hipSuccess && tour_host)
         e = hipMemcpyAsync(t.data(), c->v.gb_tour, 2 * (size_t)c->s.n, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return MMAS_EHIP;
+    if (e != hipSuccess) return hip_status(e);
     *len_host = hs.gb_len;
     if (tour_host)
         for (int k = 0; k < c->s.n; ++k) tour_host[k] = hs.gb_len >= 0 ? (int32_t)t[k] : -1;
@@ -289,7 +299,7 @@ mmas_status mmas_set_pheromone(mmas_ctx* c, const float* host_src) {
         if (!std::isfinite(host_src[e]) || host_src[e] < 0.0f) return MMAS_EINVAL;
     hipError_t e = hipMemcpyAsync(c->v.tau, host_src, c->len[MMAS_BUF_PHEROMONE], hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) return MMAS_EHIP;
+    if (e != hipSuccess) return hip_status(e);
     c->choice_stale = true;
     return MMAS_OK;
 }
@@ -299,7 +309,7 @@ mmas_status mmas_set_learned_heuristic(mmas_ctx* c, const uint16_t* knn_dev, con
     const Shape& s = c->s;
     hipError_t e = mmas::launch_install(c->v.dist, knn_dev, score_dev, c->v.cand, s.n, s.cl, s.beta,
                                         s.pher == MMAS_PHER_DENSE ? 1 : 0, c->v.heur, c->stream);
-    if (e != hipSuccess) return MMAS_EHIP;
+    if (e != hipSuccess) return hip_status(e);
     c->choice_stale = true;
     return MMAS_OK;
 }
@@ -310,6 +320,8 @@ mmas_status mmas_synchronize(mmas_ctx* c) {
 }
 
 void mmas_destroy(mmas_ctx* c) { delete c; }
+
+const char* mmas_last_error(void) { return g_last_error; }
 
 const char* mmas_status_str(mmas_status s) {
     switch (s) {

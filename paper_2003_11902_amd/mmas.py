@@ -55,7 +55,7 @@ EXPORTED = (
     "mmas_batch_capture", "mmas_batch_step", "mmas_batch_iteration", "mmas_batch_context",
     "mmas_batch_destroy", "mmas_mlp_param_count", "mmas_mlp_packed_count", "mmas_mlp_features",
     "mmas_mlp_pack", "mmas_mlp_forward", "mmas_mlp_grad", "mmas_mlp_adam", "mmas_mlp_labels",
-    "mmas_set_learned_heuristic",
+    "mmas_set_learned_heuristic", "mmas_last_error",
 )
 
 
@@ -79,7 +79,10 @@ class mmas_device_state(C.Structure):
 class MmasError(RuntimeError):
     def __init__(self, status: int, call: str):
         self.status = status
-        super().__init__(f"{call}: {status_str(status)} ({status})")
+        detail = ""
+        if status == MMAS_EHIP:
+            detail = " [" + lib.mmas_last_error().decode(errors="replace") + "]"
+        super().__init__(f"{call}: {status_str(status)} ({status}){detail}")
 
 
 def _load():
@@ -149,6 +152,8 @@ def _load():
     L.mmas_mlp_labels.restype = C.c_int
     L.mmas_set_learned_heuristic.argtypes = [p, p, p]
     L.mmas_set_learned_heuristic.restype = C.c_int
+    L.mmas_last_error.argtypes = []
+    L.mmas_last_error.restype = C.c_char_p
     L.mmas_status_str.argtypes = [C.c_int]
     L.mmas_status_str.restype = C.c_char_p
     return L

@@ -156,3 +156,25 @@ def test_labels(gpu, inst):
             j = int(knn[i, r])
             exp = sum((min(i, j), max(i, j)) in e for e in edges) / 5
             assert lab[i, r] == np.float32(exp)
+
+
+def test_pipeline_small(gpu):
+    """Training data from batched runs, a few Adam steps and the time-to-gap
+    evaluation run end to end; labels are shares of R tours (multiples of
+    1/R) and every kNN row of an instance carries its tour edges."""
+    from paper_2003_11902_amd import learned as L
+    R = 2
+    say("learned pipeline: 6 instances n in [120, 260], R=2, 5 iterations")
+    X, F = L.training_set(count=6, n_lo=120, n_hi=260, base_seed=777, R=R, iterations=5, ants=64, log=say)
+    assert X.shape[1] == 16 and X.shape[0] == F.shape[0] and X.shape[0] % 16 == 0
+    f = F.cpu().numpy()
+    assert np.all((f >= 0) & (f <= 1))
+    assert np.all(np.isin(f * R, np.arange(R + 1)))
+    # each tour has n edges, each seen from both ends when in both kNN lists:
+    # the label mass per instance is at least n (one end) per tour share
+    assert f.sum() >= 6 * 120 * 0.5
+    params, hist = L.train(X, F, epochs=2, batch=4096, log=say)
+    assert all(np.isfinite(hist))
+    xy, d = I.make_instance("uniform", 200, seed=3)
+    recs = L.time_to_gap(params, d, xy, seeds=[1], budget=20, ants=64, log=say)
+    assert len(recs) == 1 and recs[0]["plain_len"] > 0
