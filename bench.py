@@ -98,7 +98,7 @@ def run_batched(args):
               for k, d in enumerate(dists)]
     b = M.Batch(dists, params)
     setup_s = time.perf_counter() - t0
-    apb, tb = b.tune()
+    apb, tb, lanes = b.tune()
     if not args.no_graph:
         b.capture()
     for _ in range(args.warmup):
@@ -128,7 +128,7 @@ def run_batched(args):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"batched{args.batch_count}", "instances": args.batch_count,
                    "n_range": [100, 2000], "ants": "n per instance", "cand_len": 32, "rho": 0.02,
-                   "tabu": args.tabu, "graph": not args.no_graph, "ants_per_block": apb, "table_bytes": tb,
+                   "tabu": args.tabu, "graph": not args.no_graph, "ants_per_block": apb, "table_bytes": tb, "lanes_per_ant": lanes,
                    "total_ants": total_ants},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -148,6 +148,7 @@ def main():
     ap.add_argument("--ants", type=int, default=0, help="override the workload's ant count")
     ap.add_argument("--ants-per-block", type=int, default=0)
     ap.add_argument("--table-rows", type=int, default=-1)
+    ap.add_argument("--lanes-per-ant", type=int, default=64, choices=(32, 64))
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batched", action="store_true",
@@ -186,7 +187,7 @@ def main():
     n = w["n"]
     col = M.Colony(dist, w["ants"], cand_len=w["cand_len"], alpha=w["alpha"], beta=w["beta"],
                    rho=w["rho"], seed=args.seed, tabu=args.tabu, pher=w["pher"], ls_nn=w["ls_nn"])
-    col.set_launch(args.ants_per_block, args.table_rows)
+    col.set_launch(args.ants_per_block, args.table_rows, args.lanes_per_ant)
     stream = col.stream
 
     def step(it):
@@ -243,7 +244,8 @@ def main():
         "config": {"workload": args.workload, "n": n, "ants": w["ants"], "cand_len": w["cand_len"],
                    "alpha": w["alpha"], "beta": w["beta"], "rho": w["rho"], "tabu": args.tabu,
                    "pheromone": w["pher"], "instance": f"{w['kind']} seed {w['seed']}",
-                   "ants_per_block": args.ants_per_block or 4, "table_rows": args.table_rows},
+                   "ants_per_block": args.ants_per_block or 4, "table_rows": args.table_rows,
+                   "lanes_per_ant": args.lanes_per_ant},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload) if args.tabu == "bitmask" else None,

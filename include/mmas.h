@@ -85,7 +85,9 @@ typedef struct mmas_device_state {
     int64_t nn_len;    /* nearest-neighbour tour length (set-up) */
     uint32_t flags;    /* 1/2/4: distance matrix asymmetric / non-zero diagonal /
                           non-positive off the diagonal (set-up); 8: a
-                          construction step found no city (never expected) */
+                          construction step found no city (never expected);
+                          16: a 2-opt search hit its round limit (never
+                          expected; that ant's tour is left as it was) */
     uint32_t updates;  /* number of completed updates */
 } mmas_device_state;
 
@@ -140,12 +142,14 @@ mmas_status mmas_prepare_choice_info(mmas_ctx* ctx);
 mmas_status mmas_construct(mmas_ctx* ctx, uint32_t iteration);
 
 /* Launch shape of the construction kernel; results never depend on it.
- * `ants_per_block`: ants (one wave64 each) per workgroup, 1, 2, 4, 8 or 16
- * (0 = default 4; fewer are used if their LDS does not fit). `table_rows`:
- * how many rows of the candidate table (ids and choice_info) each workgroup
- * stages in LDS: -1 = as many as fit (default), 0 = none, k = at most k.
- * EINVAL for other values. */
-mmas_status mmas_set_launch(mmas_ctx* ctx, int32_t ants_per_block, int32_t table_rows);
+ * `ants_per_block`: ants per workgroup, 1, 2, 4, 8 or 16 (0 = default 4;
+ * fewer are used if their LDS does not fit). `table_rows`: how many rows of
+ * the candidate table (ids and choice_info) each workgroup stages in LDS:
+ * -1 = as many as fit (default), 0 = none, k = at most k. `lanes_per_ant`:
+ * 64 (one ant per wave64, default, also for 0) or 32 (two ants per wave64,
+ * each on a half; applies when 1 <= cand_len <= 32, with an even number of
+ * ants per workgroup, else 64 is used). EINVAL for other values. */
+mmas_status mmas_set_launch(mmas_ctx* ctx, int32_t ants_per_block, int32_t table_rows, int32_t lanes_per_ant);
 
 /* 2-opt on every ant's tour with ls_nn-nearest-neighbour lists and don't-look
  * bits (Sec. 5.7), as a sequential first-improvement search (cities in index
@@ -153,6 +157,12 @@ mmas_status mmas_set_launch(mmas_ctx* ctx, int32_t ants_per_block, int32_t table
  * first partial gain is positive; the shorter path is reversed). Updates
  * tours and lengths. EUNSUPPORTED if ls_nn == 0; ESTATE before a construct. */
 mmas_status mmas_two_opt(mmas_ctx* ctx);
+
+/* Launch shape of the 2-opt kernel; results never depend on it.
+ * `waves_per_ant`: wave64s of the workgroup that runs one ant's search, 1, 2,
+ * 4, 8 or 16 (0 = default 16); each round examines threads / (2*ls_nn
+ * rounded up to a power of two) cities. EINVAL for other values. */
+mmas_status mmas_set_two_opt_launch(mmas_ctx* ctx, int32_t waves_per_ant);
 
 /* The end of an iteration of Alg. 1: the iteration best (shortest tour,
  * lowest ant on ties); if it beats the global best (or there is none) it
@@ -207,15 +217,19 @@ mmas_status mmas_batch_create(int32_t count, const int32_t* const* dists_host, c
                               void* dev_ws, size_t ws_bytes, void* hip_stream, mmas_batch** out);
 
 /* Launch shape of the batched construction (results never depend on it):
- * `ants_per_block` 1, 2, 4, 8 or 16 ants (waves) per workgroup, and
- * `table_bytes` of LDS per workgroup for the candidate table (-1 = all that
- * is left after the ants' regions). Drops a captured graph. */
-mmas_status mmas_batch_set_launch(mmas_batch* b, int32_t ants_per_block, int32_t table_bytes);
+ * `ants_per_block` 1, 2, 4, 8 or 16 ants per workgroup, `table_bytes` of LDS
+ * per workgroup for the candidate table (-1 = all that is left after the
+ * ants' regions) and `lanes_per_ant` 64 (one ant per wave64; also 0) or 32
+ * (two ants per wave64: EUNSUPPORTED unless every instance has
+ * 1 <= cand_len <= 32 and ants_per_block >= 2). Drops a captured graph. */
+mmas_status mmas_batch_set_launch(mmas_batch* b, int32_t ants_per_block, int32_t table_bytes,
+                                  int32_t lanes_per_ant);
 
 /* Autotuner: times one construction launch for each ants_per_block in
- * {4, 8, 16} with the LDS table on and off, keeps the fastest and reports it.
+ * {4, 8, 16}, the LDS table on and off, and 64 or 32 lanes per ant (32 where
+ * allowed), keeps the fastest and reports it (any pointer may be NULL).
  * Trails are not touched. Synchronises; drops a captured graph. */
-mmas_status mmas_batch_tune(mmas_batch* b, int32_t* ants_per_block, int32_t* table_bytes);
+mmas_status mmas_batch_tune(mmas_batch* b, int32_t* ants_per_block, int32_t* table_bytes, int32_t* lanes_per_ant);
 
 /* Captures one step into a hipGraph; later steps replay it. */
 mmas_status mmas_batch_capture(mmas_batch* b);

@@ -35,6 +35,8 @@ struct mmas_batch {
     int tabu, pher;
     int per_ant;        // largest per-ant LDS region over the instances
     int ants_per_block;
+    int lanes_per_ant;
+    bool pair_ok;       // every instance has 1 <= cl <= 32
     int table_bytes;
     int ntiles;
     int grid;
@@ -85,7 +87,7 @@ mmas_status rebuild_tiles(mmas_batch* b) {
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return mmas::hip_fail(e, "tile table");
     const int lds = b->table_bytes + b->ants_per_block * b->per_ant;
-    int g = mmas::batch_construct_grid(b->tabu, b->pher, b->ants_per_block, lds);
+    int g = mmas::batch_construct_grid(b->tabu, b->pher, b->ants_per_block, b->lanes_per_ant, lds);
     if (g <= 0) return MMAS_EUNSUPPORTED;
     b->grid = std::min(g, b->ntiles);
     return MMAS_OK;
@@ -93,8 +95,8 @@ mmas_status rebuild_tiles(mmas_batch* b) {
 
 mmas_status launch_step(mmas_batch* b) {
     hipError_t e = mmas::launch_batch_construct(b->d_items, b->d_tiles, b->ntiles, b->d_queue, b->d_it, b->tabu,
-                                                b->pher, b->ants_per_block, b->table_bytes, b->per_ant, b->grid,
-                                                b->stream);
+                                                b->pher, b->ants_per_block, b->lanes_per_ant, b->table_bytes,
+                                                b->per_ant, b->grid, b->stream);
     if (e != hipSuccess) return mmas::hip_fail(e, "batched construction launch");
     e = mmas::launch_batch_update(b->d_items, b->count, b->d_row_start, b->total_rows, b->d_it, b->d_queue, b->stream);
     return e == hipSuccess ? MMAS_OK : mmas::hip_fail(e, "batched update launch");
@@ -192,7 +194,10 @@ mmas_status mmas_batch_create(int32_t count, const int32_t* const* dists_host, c
         delete b;
         return mmas::hip_fail(e, "batch tables");
     }
+    b->pair_ok = true;
+    for (int i = 0; i < count; ++i) b->pair_ok = b->pair_ok && b->items[i].s.cl >= 1 && b->items[i].s.cl <= 32;
     b->ants_per_block = 4;
+    b->lanes_per_ant = 64;
     b->table_bytes = std::max(0, (mmas::max_lds_per_block() - kStaticLds - b->ants_per_block * b->per_ant) & ~15);
     r = rebuild_tiles(b);
     if (r != MMAS_OK) {
@@ -204,41 +209,48 @@ mmas_status mmas_batch_create(int32_t count, const int32_t* const* dists_host, c
     return MMAS_OK;
 }
 
-mmas_status mmas_batch_set_launch(mmas_batch* b, int32_t ants_per_block, int32_t table_bytes) {
+mmas_status mmas_batch_set_launch(mmas_batch* b, int32_t ants_per_block, int32_t table_bytes, int32_t lanes_per_ant) {
     if (!b) return MMAS_EINVAL;
     if (ants_per_block != 1 && ants_per_block != 2 && ants_per_block != 4 && ants_per_block != 8 &&
         ants_per_block != 16)
         return MMAS_EINVAL;
+    if (lanes_per_ant != 0 && lanes_per_ant != 32 && lanes_per_ant != 64) return MMAS_EINVAL;
+    if (table_bytes < -1) return MMAS_EINVAL;
+    const int lanes = lanes_per_ant == 32 ? 32 : 64;
+    if (lanes == 32 && (!b->pair_ok || ants_per_block < 2)) return MMAS_EUNSUPPORTED;
     const int budget = (mmas::max_lds_per_block() - kStaticLds - ants_per_block * b->per_ant) & ~15;
     if (budget < 0) return MMAS_EUNSUPPORTED;
-    if (table_bytes < -1) return MMAS_EINVAL;
     drop_graph(b);
     b->ants_per_block = ants_per_block;
+    b->lanes_per_ant = lanes;
     b->table_bytes = table_bytes < 0 ? budget : std::min(budget, table_bytes & ~15);
     return rebuild_tiles(b);
 }
 
-mmas_status mmas_batch_tune(mmas_batch* b, int32_t* ants_per_block, int32_t* table_bytes) {
+mmas_status mmas_batch_tune(mmas_batch* b, int32_t* ants_per_block, int32_t* table_bytes, int32_t* lanes_per_ant) {
     if (!b) return MMAS_EINVAL;
     struct Cand {
-        int apb, tb;
+        int apb, tb, lanes;
     };
     std::vector<Cand> cands;
-    for (int apb : {4, 8, 16}) {
-        const int budget = mmas::max_lds_per_block() - kStaticLds - apb * b->per_ant;
-        if (budget < 0) continue;
-        cands.push_back({apb, -1});
-        cands.push_back({apb, 0});
+    for (int lanes : {64, 32}) {
+        if (lanes == 32 && !b->pair_ok) continue;
+        for (int apb : {4, 8, 16}) {
+            const int budget = mmas::max_lds_per_block() - kStaticLds - apb * b->per_ant;
+            if (budget < 0) continue;
+            cands.push_back({apb, -1, lanes});
+            cands.push_back({apb, 0, lanes});
+        }
     }
     hipEvent_t e0, e1;
     hipError_t ee = hipEventCreate(&e0);
     if (ee == hipSuccess) ee = hipEventCreate(&e1);
     if (ee != hipSuccess) return mmas::hip_fail(ee, "tuner events");
     float best_ms = 1e30f;
-    Cand best = cands.empty() ? Cand{4, -1} : cands[0];
+    Cand best = cands.empty() ? Cand{4, -1, 64} : cands[0];
     mmas_status r = MMAS_OK;
     for (const Cand& c : cands) {
-        r = mmas_batch_set_launch(b, c.apb, c.tb);
+        r = mmas_batch_set_launch(b, c.apb, c.tb, c.lanes);
         if (r != MMAS_OK) break;
         // construction only: it writes tours and lengths, never the trails
         float ms = 0.0f;
@@ -246,7 +258,8 @@ mmas_status mmas_batch_tune(mmas_batch* b, int32_t* ants_per_block, int32_t* tab
             k_reset_queue<<<1, 64, 0, b->stream>>>(b->d_queue);
             (void)hipEventRecord(e0, b->stream);
             ee = mmas::launch_batch_construct(b->d_items, b->d_tiles, b->ntiles, b->d_queue, b->d_it, b->tabu, b->pher,
-                                              b->ants_per_block, b->table_bytes, b->per_ant, b->grid, b->stream);
+                                              b->ants_per_block, b->lanes_per_ant, b->table_bytes, b->per_ant, b->grid,
+                                              b->stream);
             if (ee != hipSuccess) r = mmas::hip_fail(ee, "tuner launch");
             (void)hipEventRecord(e1, b->stream);
             ee = hipEventSynchronize(e1);
@@ -262,10 +275,11 @@ mmas_status mmas_batch_tune(mmas_batch* b, int32_t* ants_per_block, int32_t* tab
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (r != MMAS_OK) return r;
-    r = mmas_batch_set_launch(b, best.apb, best.tb);
+    r = mmas_batch_set_launch(b, best.apb, best.tb, best.lanes);
     if (r != MMAS_OK) return r;
     if (ants_per_block) *ants_per_block = b->ants_per_block;
     if (table_bytes) *table_bytes = b->table_bytes;
+    if (lanes_per_ant) *lanes_per_ant = b->lanes_per_ant;
     ee = hipStreamSynchronize(b->stream);
     return ee == hipSuccess ? MMAS_OK : mmas::hip_fail(ee, "tuner synchronisation");
 }

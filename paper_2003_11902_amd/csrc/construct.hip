@@ -249,23 +249,21 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
             }
             const int j = (k - 1) & (S - 1);
             if (j == 0) {
+                // (steps past n - 1 draw values nobody reads; no lane is masked)
                 const int ks = k + (lane >> gsh);
-                if (ks < n) {
-                    const Words4 b = draw_block(seed, it, (uint32_t)ant, (uint32_t)ks,
-                                                (uint32_t)(4 * (lane & (G - 1))));
-                    float4 lv;
-                    lv.x = log_u01(u01(b.w[0]));
-                    lv.y = log_u01(u01(b.w[1]));
-                    lv.z = log_u01(u01(b.w[2]));
-                    lv.w = log_u01(u01(b.w[3]));
-                    *reinterpret_cast<float4*>(lnbuf + 4 * lane) = lv;
-                }
+                const Words4 b = draw_block(seed, it, (uint32_t)ant, (uint32_t)ks, (uint32_t)(4 * (lane & (G - 1))));
+                float4 lv;
+                lv.x = log_u01(u01(b.w[0]));
+                lv.y = log_u01(u01(b.w[1]));
+                lv.z = log_u01(u01(b.w[2]));
+                lv.w = log_u01(u01(b.w[3]));
+                *reinterpret_cast<float4*>(lnbuf + 4 * lane) = lv;
             }
             // branch-free: every lane of the list computes its key; visited
             // cities and lanes past the list contribute no key
             const float lnu = lnbuf[4 * j * G + (lane & (4 * G - 1))];
             const float key = lnu / w;
-            const bool live = lane < cl && !tabu.visited(node);
+            const bool live = (lane < cl) & !tabu.visited(node);  // no short circuit: no exec mask
             const uint32_t code = live ? ord_key(key) : 0u;
             next = cl <= 32 ? wave_select<2>(code, node) : wave_select<4>(code, node);
         }
@@ -321,7 +319,193 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
     }
 }
 
+// Per-half wave64 reductions for two ants per wave (lanes 0-31: first ant,
+// 32-63: second): the maximum (minimum) of each half, as two scalars.
+__device__ __forceinline__ void half_max_u32(uint32_t x, uint32_t& lo, uint32_t& hi) {
+    x = max(x, dpp<0xB1>(x));
+    x = max(x, dpp<0x4E>(x));
+    x = max(x, dpp<0x141>(x));
+    x = max(x, dpp<0x140>(x));
+    lo = max((uint32_t)__builtin_amdgcn_readlane((int)x, 0), (uint32_t)__builtin_amdgcn_readlane((int)x, 16));
+    hi = max((uint32_t)__builtin_amdgcn_readlane((int)x, 32), (uint32_t)__builtin_amdgcn_readlane((int)x, 48));
+}
+__device__ __forceinline__ void half_min_u32(uint32_t x, uint32_t& lo, uint32_t& hi) {
+    x = min(x, dpp<0xB1>(x));
+    x = min(x, dpp<0x4E>(x));
+    x = min(x, dpp<0x141>(x));
+    x = min(x, dpp<0x140>(x));
+    lo = min((uint32_t)__builtin_amdgcn_readlane((int)x, 0), (uint32_t)__builtin_amdgcn_readlane((int)x, 16));
+    hi = min((uint32_t)__builtin_amdgcn_readlane((int)x, 32), (uint32_t)__builtin_amdgcn_readlane((int)x, 48));
+}
+
+// The all-node fallback of one ant (whole wave), as in construct_ant.
+template <int kTabu, int kPher, class Tabu>
+__device__ uint32_t fallback_step(const Views& vw, const Shape& s, uint32_t it, uint32_t ant, uint32_t cur, int k,
+                                  const Tabu& tabu, uint8_t* region, float tmin_a, int lane) {
+    const int n = s.n;
+    const uint16_t* list;
+    int L;
+    if constexpr (kTabu == MMAS_TABU_BITMASK) {
+        uint16_t* ulist = reinterpret_cast<uint16_t*>(region + kDrawBytes + kScratchBytes + align16(4 * ((n + 31) / 32)));
+        L = gather_unvisited(tabu, n, ulist, reinterpret_cast<uint32_t*>(region + kDrawBytes), lane);
+        list = ulist;
+    } else {
+        L = tabu.L;
+        list = tabu.entries;
+    }
+    if constexpr (kPher == MMAS_PHER_DENSE) {
+        const DenseWeight wt{vw.choice + (size_t)cur * n};
+        return fallback_list(list, L, wt, s.cl, s.seed, it, ant, (uint32_t)k, lane);
+    } else {
+        const CandWeight wt{vw.dist + (size_t)cur * n, tmin_a, s.beta};
+        return fallback_list(list, L, wt, s.cl, s.seed, it, ant, (uint32_t)k, lane);
+    }
+}
+
+// Two ants per wave64 (1 <= cl <= 32): lanes 0-31 serve ant `ant0`, lanes
+// 32-63 ant `ant0 + 1` (absent if !hasB). Both take their candidate steps
+// together: lane 32h + r holds rank r of ant h's current row, the keys and
+// the per-half argmax are those of construct_ant. A step in which an ant has
+// no unvisited candidate runs that ant's fallback on the whole wave. Same
+// draws, same arithmetic, same tours as one ant per wave.
 template <int kTabu, int kPher>
+__device__ void construct_pair(const Views& vw, const Shape& s, uint32_t it, int ant0, bool hasB, int lane,
+                               uint8_t* regA, uint8_t* regB, const uint16_t* tcand, const float* tchc, int R) {
+    using Tabu = typename TabuOf<kTabu>::type;
+    const int n = s.n, cl = s.cl;
+    const uint64_t seed = s.seed;
+    const int h = lane >> 5, hl = lane & 31;
+    const uint32_t antA = (uint32_t)ant0, antB = (uint32_t)ant0 + 1u;
+    const uint32_t my_ant = h ? antB : antA;
+
+    Tabu tabA, tabB;
+    tabA.init(regA + kDrawBytes + kScratchBytes, n, lane);
+    tabB.init(regB + kDrawBytes + kScratchBytes, n, lane);
+    float* lnbuf = reinterpret_cast<float*>(h ? regB : regA);
+
+    float tmin_a = 0.0f;
+    if (kPher == MMAS_PHER_CANDIDATES) tmin_a = powi(vw.state->tau_min, s.alpha);
+    const LdsPtr<const uint16_t> lds_cand = (LdsPtr<const uint16_t>)tcand;
+    const LdsPtr<const float> lds_chc = (LdsPtr<const float>)tchc;
+    const GlbPtr<const uint16_t> glb_cand = (GlbPtr<const uint16_t>)vw.cand;
+    const GlbPtr<const float> glb_chc = (GlbPtr<const float>)vw.chc;
+
+    // start cities: floor(x * n / 2^32) of draw (step 0, slot 0) of each ant
+    const uint32_t x0 = draw_block(seed, it, my_ant, 0u, 0u).w[0];
+    const uint32_t st_l = (uint32_t)(((uint64_t)x0 * (uint64_t)n) >> 32);
+    const uint32_t startA = (uint32_t)__builtin_amdgcn_readlane((int)st_l, 0);
+    const uint32_t startB = (uint32_t)__builtin_amdgcn_readlane((int)st_l, 32);
+    tabA.mark(startA, lane);
+    if (hasB) tabB.mark(startB, lane ^ 32);
+
+    // draws ahead, S = 32/G steps at a time, each half for its own ant
+    const int gsh = cl <= 4 ? 0 : cl <= 8 ? 1 : cl <= 16 ? 2 : 3;
+    const int G = 1 << gsh;
+    const int S = 32 >> gsh;
+
+    uint16_t* tour_out = vw.tours + (size_t)my_ant * n;
+    const int32_t* dist = vw.dist;
+    const bool writer = h == 0 || hasB;
+    uint32_t tbuf = h ? startB : startA;  // lane 32h + (k & 31) holds the city of step k
+    uint32_t prev_last = 0;
+    int64_t len = 0;
+    int64_t fbA_steps = 0, fbA_nodes = 0, fbB_steps = 0, fbB_nodes = 0;
+    uint32_t curA = startA, curB = startB;
+
+    for (int k = 1; k < n; ++k) {
+        const uint32_t cur_l = h ? curB : curA;
+        const int e = (int)cur_l * cl + (hl < cl ? hl : cl - 1);
+        uint32_t node;
+        float w;
+        if ((int)cur_l < R) {
+            node = lds_cand[e];
+            w = lds_chc[e];
+        } else {
+            node = glb_cand[e];
+            w = glb_chc[e];
+        }
+        const int j = (k - 1) & (S - 1);
+        if (j == 0) {
+            const int ks = k + (hl >> gsh);
+            const Words4 b = draw_block(seed, it, my_ant, (uint32_t)ks, (uint32_t)(4 * (hl & (G - 1))));
+            float4 lv;
+            lv.x = log_u01(u01(b.w[0]));
+            lv.y = log_u01(u01(b.w[1]));
+            lv.z = log_u01(u01(b.w[2]));
+            lv.w = log_u01(u01(b.w[3]));
+            *reinterpret_cast<float4*>(lnbuf + 4 * hl) = lv;
+        }
+        const float lnu = lnbuf[4 * j * G + (hl & (4 * G - 1))];
+        const float key = lnu / w;
+        const Tabu mine = h ? tabB : tabA;  // this half's tabu
+        const bool live = (hl < cl) & !mine.visited(node) & writer;
+        const uint32_t code = live ? ord_key(key) : 0u;
+        uint32_t bestA, bestB;
+        half_max_u32(code, bestA, bestB);
+        const uint32_t best_l = h ? bestB : bestA;
+        const uint64_t tied = __ballot(live && code == best_l);
+        const uint32_t tA = (uint32_t)tied, tB = (uint32_t)(tied >> 32);
+        uint32_t nextA = kNone, nextB = kNone;
+        if (__popc(tA) > 1 || __popc(tB) > 1) {
+            uint32_t mA, mB;
+            half_min_u32(((tied >> lane) & 1ull) ? node : kNone, mA, mB);
+            nextA = mA;
+            nextB = mB;
+        } else {
+            if (tA) nextA = (uint32_t)__builtin_amdgcn_readlane((int)node, __ffs(tA) - 1);
+            if (tB) nextB = (uint32_t)__builtin_amdgcn_readlane((int)node, 32 + __ffs(tB) - 1);
+        }
+        if (nextA == kNone) {
+            fbA_steps += 1;
+            fbA_nodes += n - k;
+            nextA = fallback_step<kTabu, kPher>(vw, s, it, antA, curA, k, tabA, regA, tmin_a, lane);
+        }
+        if (!hasB) {
+            nextB = curB;  // an absent second ant stays at its (valid) start city
+        } else if (nextB == kNone) {
+            fbB_steps += 1;
+            fbB_nodes += n - k;
+            nextB = fallback_step<kTabu, kPher>(vw, s, it, antB, curB, k, tabB, regB, tmin_a, lane);
+        }
+        if (nextA >= (uint32_t)n || nextB >= (uint32_t)n) {
+            if (lane == 0) atomicOr(&vw.state->flags, 8u);
+            break;
+        }
+        tabA.mark(nextA, lane);
+        if (hasB) tabB.mark(nextB, lane ^ 32);
+        const int slot = k & 31;
+        if (hl == slot) tbuf = h ? nextB : nextA;
+        curA = nextA;
+        curB = nextB;
+        if (slot == 31 || k == n - 1) {
+            const int k0 = k - slot;
+            const uint32_t prev = __shfl_up(tbuf, 1);
+            if (hl <= slot && writer) {
+                tour_out[k0 + hl] = (uint16_t)tbuf;
+                const uint32_t from = hl == 0 ? prev_last : prev;
+                if (k0 + hl > 0) len += dist[(size_t)from * n + tbuf];
+            }
+            const uint32_t plA = (uint32_t)__builtin_amdgcn_readlane((int)tbuf, slot);
+            const uint32_t plB = (uint32_t)__builtin_amdgcn_readlane((int)tbuf, 32 + slot);
+            prev_last = h ? plB : plA;
+        }
+    }
+    if (lane == 0) len += dist[(size_t)curA * n + startA];  // closing edges
+    if (lane == 32 && hasB) len += dist[(size_t)curB * n + startB];
+    for (int o = 16; o >= 1; o >>= 1) len += __shfl_xor(len, o);
+    if (lane == 0) {
+        vw.lengths[antA] = len;
+        vw.fallback[antA] = fbA_steps;
+        vw.fallback[s.ants + antA] = fbA_nodes;
+    }
+    if (lane == 32 && hasB) {
+        vw.lengths[antB] = len;
+        vw.fallback[antB] = fbB_steps;
+        vw.fallback[s.ants + antB] = fbB_nodes;
+    }
+}
+
+template <int kTabu, int kPher, bool kPair>
 __global__ __launch_bounds__(1024) void k_construct(Views vw, Shape s, uint32_t it, int ants_per_block, Lds lds) {
     extern __shared__ __align__(16) uint8_t smem[];
     const int lane = threadIdx.x & 63;
@@ -333,17 +517,21 @@ __global__ __launch_bounds__(1024) void k_construct(Views vw, Shape s, uint32_t 
         stage_table(vw, s.cl, R, tcand, tchc);
         __syncthreads();
     }
-    const int ant = blockIdx.x * ants_per_block + wave;
+    const int ant = blockIdx.x * ants_per_block + (kPair ? 2 * wave : wave);
     if (ant >= s.ants) return;  // whole waves leave together
-    construct_ant<kTabu, kPher>(vw, s, it, ant, lane, smem + lds.table_bytes + (size_t)wave * lds.per_ant, tcand,
-                                tchc, R);
+    uint8_t* regions = smem + lds.table_bytes;
+    if constexpr (kPair)
+        construct_pair<kTabu, kPher>(vw, s, it, ant, ant + 1 < s.ants, lane, regions + (size_t)(2 * wave) * lds.per_ant,
+                                     regions + (size_t)(2 * wave + 1) * lds.per_ant, tcand, tchc, R);
+    else
+        construct_ant<kTabu, kPher>(vw, s, it, ant, lane, regions + (size_t)wave * lds.per_ant, tcand, tchc, R);
 }
 
 // Batched construction: a persistent grid pulls tiles (instance, first ant of
 // a group of ants_per_block ants) from a queue ordered by decreasing n. Each
 // tile stages as many candidate rows of its instance as fit in the table part
-// of LDS, then every wave builds one ant's tour.
-template <int kTabu, int kPher>
+// of LDS, then every wave builds one ant's tour (two with kPair).
+template <int kTabu, int kPher, bool kPair>
 __global__ __launch_bounds__(1024) void k_batch_construct(const BatchItem* __restrict__ items,
                                                           const BatchTile* __restrict__ tiles, int ntiles,
                                                           uint32_t* __restrict__ queue, const uint32_t* __restrict__ it_dev,
@@ -371,10 +559,16 @@ __global__ __launch_bounds__(1024) void k_batch_construct(const BatchItem* __res
         float* tchc = reinterpret_cast<float*>(smem + align16(R * s.cl * 2));
         if (R > 0) stage_table(vw, s.cl, R, tcand, tchc);
         __syncthreads();
-        const int ant = tile.ant0 + wave;
-        if (ant < s.ants)
-            construct_ant<kTabu, kPher>(vw, s, it, ant, lane, smem + table_bytes + (size_t)wave * per_ant, tcand,
-                                        tchc, R);
+        const int ant = tile.ant0 + (kPair ? 2 * wave : wave);
+        uint8_t* regions = smem + table_bytes;
+        if (ant < s.ants) {
+            if constexpr (kPair)
+                construct_pair<kTabu, kPher>(vw, s, it, ant, ant + 1 < s.ants, lane,
+                                             regions + (size_t)(2 * wave) * per_ant,
+                                             regions + (size_t)(2 * wave + 1) * per_ant, tcand, tchc, R);
+            else
+                construct_ant<kTabu, kPher>(vw, s, it, ant, lane, regions + (size_t)wave * per_ant, tcand, tchc, R);
+        }
         __syncthreads();  // the next tile reuses the table part
     }
 }
@@ -396,12 +590,18 @@ int max_lds_per_block() {
 
 namespace {
 
-template <int kTabu, int kPher>
+// Two ants per wave when asked for and 1 <= cl <= 32 (the candidate row fits
+// in a half wave).
+bool pair_ok(const Shape& s) { return s.lanes_per_ant == 32 && s.cl >= 1 && s.cl <= 32; }
+
+template <int kTabu, int kPher, bool kPair>
 hipError_t launch_t(const Views& v, const Shape& s, uint32_t it, hipStream_t st) {
     const int per_ant = (int)construct_lds_per_ant(s);
     const int budget = max_lds_per_block();
     int apb = s.ants_per_block > 0 ? s.ants_per_block : 4;
-    while (apb > 1 && per_ant * apb > budget) --apb;
+    const int step = kPair ? 2 : 1;  // ants per wave
+    if (apb < step) apb = step;
+    while (apb > step && per_ant * apb > budget) apb -= step;
     if (per_ant * apb > budget) return hipErrorInvalidValue;
     // as many rows of the candidate table as fit next to the ants' regions
     Lds lds{};
@@ -418,14 +618,35 @@ hipError_t launch_t(const Views& v, const Shape& s, uint32_t it, hipStream_t st)
     lds.rows = rows;
     lds.table_bytes = align16(rows * s.cl * 2) + align16(rows * s.cl * 4);
     const size_t bytes = (size_t)lds.table_bytes + (size_t)apb * per_ant;
-    auto kern = k_construct<kTabu, kPher>;
+    auto kern = k_construct<kTabu, kPher, kPair>;
     if (bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
     }
     const int blocks = (s.ants + apb - 1) / apb;
-    kern<<<blocks, 64 * apb, bytes, st>>>(v, s, it, apb, lds);
+    kern<<<blocks, 64 * (apb / step), bytes, st>>>(v, s, it, apb, lds);
     return hipGetLastError();
+}
+
+template <int kTabu, int kPher>
+hipError_t launch_tp(const Views& v, const Shape& s, uint32_t it, hipStream_t st) {
+    return pair_ok(s) ? launch_t<kTabu, kPher, true>(v, s, it, st) : launch_t<kTabu, kPher, false>(v, s, it, st);
+}
+
+// the persistent batched kernel for a configuration
+const void* batch_kernel(int tabu, int pher, bool pair) {
+    if (tabu == MMAS_TABU_BITMASK) {
+        if (pher == MMAS_PHER_DENSE)
+            return pair ? (const void*)k_batch_construct<MMAS_TABU_BITMASK, MMAS_PHER_DENSE, true>
+                        : (const void*)k_batch_construct<MMAS_TABU_BITMASK, MMAS_PHER_DENSE, false>;
+        return pair ? (const void*)k_batch_construct<MMAS_TABU_BITMASK, MMAS_PHER_CANDIDATES, true>
+                    : (const void*)k_batch_construct<MMAS_TABU_BITMASK, MMAS_PHER_CANDIDATES, false>;
+    }
+    if (pher == MMAS_PHER_DENSE)
+        return pair ? (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_DENSE, true>
+                    : (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_DENSE, false>;
+    return pair ? (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_CANDIDATES, true>
+                : (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_CANDIDATES, false>;
 }
 
 }  // namespace
@@ -439,38 +660,29 @@ size_t construct_lds_per_ant(const Shape& s) {
 }
 
 hipError_t launch_batch_construct(const BatchItem* items, const BatchTile* tiles, int ntiles, uint32_t* queue,
-                                  const uint32_t* it_dev, int tabu, int pher, int ants_per_block, int table_bytes,
-                                  int per_ant, int grid, hipStream_t st) {
+                                  const uint32_t* it_dev, int tabu, int pher, int ants_per_block, int lanes_per_ant,
+                                  int table_bytes, int per_ant, int grid, hipStream_t st) {
     const size_t bytes = (size_t)table_bytes + (size_t)ants_per_block * per_ant;
-    const void* kern;
-    if (tabu == MMAS_TABU_BITMASK)
-        kern = pher == MMAS_PHER_DENSE ? (const void*)k_batch_construct<MMAS_TABU_BITMASK, MMAS_PHER_DENSE>
-                                       : (const void*)k_batch_construct<MMAS_TABU_BITMASK, MMAS_PHER_CANDIDATES>;
-    else
-        kern = pher == MMAS_PHER_DENSE ? (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_DENSE>
-                                       : (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_CANDIDATES>;
+    const bool pair = lanes_per_ant == 32;
+    const void* kern = batch_kernel(tabu, pher, pair);
     // the LDS limit was raised by batch_construct_grid for this footprint (a
     // graph capture must not need it here)
     void* args[] = {(void*)&items, (void*)&tiles, (void*)&ntiles, (void*)&queue, (void*)&it_dev,
                     (void*)&ants_per_block, (void*)&table_bytes, (void*)&per_ant};
-    return hipLaunchKernel(kern, dim3(grid), dim3(64 * ants_per_block), args, bytes, st);
+    return hipLaunchKernel(kern, dim3(grid), dim3(64 * (pair ? ants_per_block / 2 : ants_per_block)), args, bytes, st);
 }
 
-int batch_construct_grid(int tabu, int pher, int ants_per_block, int lds_bytes) {
-    const void* kern;
-    if (tabu == MMAS_TABU_BITMASK)
-        kern = pher == MMAS_PHER_DENSE ? (const void*)k_batch_construct<MMAS_TABU_BITMASK, MMAS_PHER_DENSE>
-                                       : (const void*)k_batch_construct<MMAS_TABU_BITMASK, MMAS_PHER_CANDIDATES>;
-    else
-        kern = pher == MMAS_PHER_DENSE ? (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_DENSE>
-                                       : (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_CANDIDATES>;
+int batch_construct_grid(int tabu, int pher, int ants_per_block, int lanes_per_ant, int lds_bytes) {
+    const bool pair = lanes_per_ant == 32;
+    const void* kern = batch_kernel(tabu, pher, pair);
     if (lds_bytes > 64 * 1024 &&
         hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes) != hipSuccess) {
         (void)hipGetLastError();  // do not leave the error for the next launch check
         return 0;
     }
     int per_cu = 0, dev = 0, cus = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * ants_per_block, lds_bytes) != hipSuccess) {
+    const int threads = 64 * (pair ? ants_per_block / 2 : ants_per_block);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds_bytes) != hipSuccess) {
         (void)hipGetLastError();
         return 0;
     }
@@ -482,11 +694,11 @@ int batch_construct_grid(int tabu, int pher, int ants_per_block, int lds_bytes) 
 
 hipError_t launch_construct(const Views& v, const Shape& s, uint32_t it, hipStream_t st) {
     if (s.tabu == MMAS_TABU_BITMASK) {
-        return s.pher == MMAS_PHER_DENSE ? launch_t<MMAS_TABU_BITMASK, MMAS_PHER_DENSE>(v, s, it, st)
-                                         : launch_t<MMAS_TABU_BITMASK, MMAS_PHER_CANDIDATES>(v, s, it, st);
+        return s.pher == MMAS_PHER_DENSE ? launch_tp<MMAS_TABU_BITMASK, MMAS_PHER_DENSE>(v, s, it, st)
+                                         : launch_tp<MMAS_TABU_BITMASK, MMAS_PHER_CANDIDATES>(v, s, it, st);
     }
-    return s.pher == MMAS_PHER_DENSE ? launch_t<MMAS_TABU_COMPACT, MMAS_PHER_DENSE>(v, s, it, st)
-                                     : launch_t<MMAS_TABU_COMPACT, MMAS_PHER_CANDIDATES>(v, s, it, st);
+    return s.pher == MMAS_PHER_DENSE ? launch_tp<MMAS_TABU_COMPACT, MMAS_PHER_DENSE>(v, s, it, st)
+                                     : launch_tp<MMAS_TABU_COMPACT, MMAS_PHER_CANDIDATES>(v, s, it, st);
 }
 
 }  // namespace mmas

@@ -42,8 +42,10 @@ struct Shape {
     float rho;
     double pdec; // p_best^(1/n)
     uint64_t seed;
-    int ants_per_block;  // construction launch: ants (waves) per workgroup
+    int ants_per_block;  // construction launch: ants per workgroup
+    int lanes_per_ant;   // construction launch: 64 (one ant per wave) or 32 (two)
     int table_rows;      // rows of the candidate table staged in LDS (-1: all that fit)
+    int two_opt_waves;   // 2-opt launch: waves per ant (1..16)
 };
 
 // One instance of a batch (device array, one entry per instance).
@@ -80,11 +82,13 @@ hipError_t launch_update(const Views& v, const Shape& s, hipStream_t st);       
 // ---- batches (one launch per step for all instances) ----
 // construct.hip: persistent construction over `ntiles` tiles; `queue` must be
 // 0 at launch (the batched best kernel re-arms it).
+// lanes_per_ant 32 (two ants per wave, ants_per_block even) needs 1 <= cl <= 32
+// in every instance.
 hipError_t launch_batch_construct(const BatchItem* items, const BatchTile* tiles, int ntiles, uint32_t* queue,
-                                  const uint32_t* it_dev, int tabu, int pher, int ants_per_block, int table_bytes,
-                                  int per_ant, int grid, hipStream_t st);
+                                  const uint32_t* it_dev, int tabu, int pher, int ants_per_block, int lanes_per_ant,
+                                  int table_bytes, int per_ant, int grid, hipStream_t st);
 // Persistent-grid size for this LDS footprint (workgroups that fit at once).
-int batch_construct_grid(int tabu, int pher, int ants_per_block, int lds_bytes);
+int batch_construct_grid(int tabu, int pher, int ants_per_block, int lanes_per_ant, int lds_bytes);
 // update.hip: best/limits for every instance (one workgroup each), then the
 // fused update of every row of every instance (`row_start` = prefix sums of
 // the instances' row counts, count + 1 entries); increments *it_dev and
@@ -112,6 +116,8 @@ hipError_t launch_labels(const uint16_t* tours, int R, int n, const uint16_t* kn
 // LDS bytes one ant needs in the construction kernel (0 if it cannot run).
 size_t construct_lds_per_ant(const Shape& s);
 // LDS bytes of the 2-opt kernel (one tour per workgroup).
-size_t two_opt_lds_bytes(const Shape& s);
+size_t two_opt_lds_bytes(const Shape& s, bool with_len);
+// LDS the 2-opt kernel declares statically (city list, per-wave records)
+constexpr size_t kTwoOptStaticLds = 4096;
 
 }  // namespace mmas

@@ -65,6 +65,8 @@ Shape shape_of(const mmas_params* p) {
     s.seed = p->seed;
     s.ants_per_block = 4;
     s.table_rows = -1;
+    s.lanes_per_ant = 64;
+    s.two_opt_waves = 16;
     return s;
 }
 
@@ -162,7 +164,7 @@ mmas_status mmas_create(const int32_t* dist_host, const mmas_params* p, void* de
             return mmas::hip_fail(e, "device query");
         }
         if (mmas::construct_lds_per_ant(s) > (size_t)maxlds ||
-            (s.ls_nn > 0 && mmas::two_opt_lds_bytes(s) > (size_t)maxlds)) {
+            (s.ls_nn > 0 && mmas::two_opt_lds_bytes(s, false) + mmas::kTwoOptStaticLds > (size_t)maxlds)) {
             delete c;
             return MMAS_EUNSUPPORTED;
         }
@@ -233,14 +235,25 @@ mmas_status mmas_construct(mmas_ctx* c, uint32_t iteration) {
     return MMAS_OK;
 }
 
-mmas_status mmas_set_launch(mmas_ctx* c, int32_t ants_per_block, int32_t table_rows) {
+mmas_status mmas_set_launch(mmas_ctx* c, int32_t ants_per_block, int32_t table_rows, int32_t lanes_per_ant) {
     if (!c) return MMAS_EINVAL;
     if (ants_per_block != 0 && ants_per_block != 1 && ants_per_block != 2 && ants_per_block != 4 &&
         ants_per_block != 8 && ants_per_block != 16)
         return MMAS_EINVAL;
     if (table_rows < -1) return MMAS_EINVAL;
+    if (lanes_per_ant != 0 && lanes_per_ant != 32 && lanes_per_ant != 64) return MMAS_EINVAL;
     c->s.ants_per_block = ants_per_block == 0 ? 4 : ants_per_block;
     c->s.table_rows = table_rows;
+    c->s.lanes_per_ant = lanes_per_ant == 0 ? 64 : lanes_per_ant;
+    return MMAS_OK;
+}
+
+mmas_status mmas_set_two_opt_launch(mmas_ctx* c, int32_t waves_per_ant) {
+    if (!c) return MMAS_EINVAL;
+    if (waves_per_ant != 0 && waves_per_ant != 1 && waves_per_ant != 2 && waves_per_ant != 4 && waves_per_ant != 8 &&
+        waves_per_ant != 16)
+        return MMAS_EINVAL;
+    c->s.two_opt_waves = waves_per_ant == 0 ? 16 : waves_per_ant;
     return MMAS_OK;
 }
 

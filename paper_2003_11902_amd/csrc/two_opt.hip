@@ -1,6 +1,6 @@
 // 2-opt on every ant's tour with neighbour lists and don't-look bits
-// (Sec. 5.7, after Bentley), one wave64 per ant, tour and position arrays in
-// LDS.
+// (Sec. 5.7, after Bentley): one workgroup per ant, tour, position, edge
+// lengths and don't-look bits in LDS.
 //
 // The result is that of the sequential first-improvement search: cities are
 // examined in index order, cyclically, skipping those whose don't-look bit is
@@ -12,7 +12,8 @@
 // positive total gain is the move the sequential search would take. The move
 // reverses the shorter of its two paths (the one starting next to a on a
 // tie), its four end points get their bits cleared and a is examined again;
-// a city without a move gets its bit set.
+// a city without a move gets its bit set. Several cities are evaluated per
+// round (see k_two_opt), which changes the speed and not the result.
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -23,149 +24,263 @@ __device__ __forceinline__ int64_t dd(const int32_t* dist, int n, uint32_t x, ui
     return (int64_t)dist[(size_t)x * n + y];
 }
 
-// reverse the cyclic path of positions i..j (inclusive) in parallel
-__device__ void reverse_path(uint16_t* tour, uint16_t* pos, int n, int i, int j, int lane) {
-    const int len = ((j - i + n) % n) + 1;
-    for (int t = lane; t < len / 2; t += kWave) {
-        int p = i + t;
-        if (p >= n) p -= n;
-        int q = j - t;
-        if (q < 0) q += n;
-        const uint16_t tp = tour[p], tq = tour[q];
-        tour[p] = tq;
-        tour[q] = tp;
-        pos[tq] = (uint16_t)p;
-        pos[tp] = (uint16_t)q;
-    }
+constexpr int kMaxWaves = 16;
+constexpr int kMaxList = 512;  // cities examined per round (1024 threads / groups of >= 2)
+
+struct Cand {
+    int key;                 // (list index << 6) | lane in group; INT_MAX if none
+    int a, a1, c, c1;
+    int i, j;                // cyclic position range to reverse
+    int dac, da1c1;          // lengths of the two new edges
+};
+
+// Inclusive prefix sum over the wave: row scans by DPP, row totals by readlane.
+__device__ __forceinline__ int wave_incl_scan(int x, int lane) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
+    const int r0 = __builtin_amdgcn_readlane(x, 15);
+    const int r1 = __builtin_amdgcn_readlane(x, 31);
+    const int r2 = __builtin_amdgcn_readlane(x, 47);
+    const int row = lane >> 4;
+    x += (row >= 1 ? r0 : 0) + (row >= 2 ? r1 : 0) + (row >= 3 ? r2 : 0);
+    return x;
 }
 
-// first city at or after `a` (cyclically) whose don't-look bit is clear;
-// the caller guarantees one exists
-__device__ int next_active(const uint32_t* dlb, int n, int a, int lane) {
-    const int words = (n + 31) >> 5;
-    const int w0 = a >> 5;
-    const uint32_t first = ~dlb[w0] & (0xFFFFFFFFu << (a & 31));
-    uint32_t lastmask = (n & 31) ? ((1u << (n & 31)) - 1u) : 0xFFFFFFFFu;
-    if (w0 == words - 1) {
-        const uint32_t f = first & lastmask;
-        if (f) return w0 * 32 + __ffs(f) - 1;
-    } else if (first) {
-        return w0 * 32 + __ffs(first) - 1;
-    }
-    // the following words, cyclically (ending with w0 itself, whole)
-    for (int base = 1; base <= words; base += kWave) {
-        const int off = base + lane;
-        uint32_t fr = 0u;
-        if (off <= words) {
-            const int w = (w0 + off) % words;
-            fr = ~dlb[w];
-            if (w == words - 1) fr &= lastmask;
-        }
-        const uint64_t m = __ballot(fr != 0u);
-        if (m) {
-            const int l = __ffsll((unsigned long long)m) - 1;
-            const int w = (w0 + base + l) % words;
-            const uint32_t f = (uint32_t)__builtin_amdgcn_readlane((int)fr, l);
-            return w * 32 + __ffs(f) - 1;
-        }
-    }
-    return a;  // not reached
-}
-
-__global__ __launch_bounds__(64) void k_two_opt(Views vw, Shape s, const int32_t* __restrict__ nnd) {
+// The 2-opt of one ant per workgroup. kLen: the tour's edge lengths are kept
+// in LDS by position (len[p] = d(tour[p], tour[p+1])), so a move evaluation
+// reads one distance from HBM instead of three.
+//
+// A round examines the next C active cities in cyclic index order (C =
+// threads / group, a group of 2k lanes per city) against the current tour.
+// The first of them (in that order) with an improving move is the city the
+// sequential search reaches next with a move: the cities before it have none
+// and get their bits set, its move is applied and it is examined again. With
+// no move among the C, all C get their bits set.
+template <bool kLen>
+__global__ __launch_bounds__(1024) void k_two_opt(Views vw, Shape s, const int32_t* __restrict__ nnd) {
     extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ uint16_t s_list[kMaxList];
+    __shared__ int s_wsum[kMaxWaves];
+    __shared__ Cand s_cand[kMaxWaves];
+    __shared__ int s_active, s_cursor;
+    __shared__ unsigned long long s_len;
     const int n = s.n, k = s.ls_nn;
     const int ant = blockIdx.x;
-    const int lane = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int nthr = blockDim.x, nwaves = nthr >> 6;
+    int gs = 1;
+    while (gs < 2 * k) gs <<= 1;  // lanes per city (power of two <= 64)
+    const int C = min(nthr / gs, kMaxList);
     uint16_t* tour = reinterpret_cast<uint16_t*>(smem);
     uint16_t* pos = tour + n;
-    uint32_t* dlb = reinterpret_cast<uint32_t*>(smem + ((4 * n + 15) & ~15));
+    const size_t tp_bytes = (4 * (size_t)n + 15) & ~(size_t)15;
+    int32_t* elen = reinterpret_cast<int32_t*>(smem + tp_bytes);
+    uint32_t* dlb = reinterpret_cast<uint32_t*>(smem + tp_bytes + (kLen ? 4 * (size_t)n : 0));
     const int words = (n + 31) >> 5;
+    const uint32_t lastmask = (n & 31) ? ((1u << (n & 31)) - 1u) : 0xFFFFFFFFu;
     const int32_t* dist = vw.dist;
     const uint16_t* nn = vw.lsnn;
     uint16_t* gtour = vw.tours + (size_t)ant * n;
+    // after a failed construction the tour may not be a permutation
+    if (vw.state->flags & 8u) return;
 
-    for (int i = lane; i < n; i += kWave) {
-        const uint16_t t = gtour[i];
-        tour[i] = t;
-        pos[t] = (uint16_t)i;
+    for (int i = t; i < n; i += nthr) {
+        const uint16_t v = gtour[i];
+        tour[i] = v;
+        pos[v] = (uint16_t)i;
     }
-    for (int w = lane; w < words; w += kWave) dlb[w] = 0u;
+    for (int w = t; w < words; w += nthr) dlb[w] = 0u;
+    if (t == 0) {
+        s_active = n;
+        s_cursor = 0;
+        s_len = 0ull;
+    }
+    __syncthreads();
+    if (kLen)
+        for (int i = t; i < n; i += nthr) elen[i] = dist[(size_t)tour[i] * n + tour[i + 1 == n ? 0 : i + 1]];
 
-    int active = n;  // cities whose bit is clear (uniform)
-    int a = 0;
-    while (active > 0) {
-        a = next_active(dlb, n, a, lane);
-        const int pa = pos[a];
-        const uint32_t asucc = tour[pa + 1 == n ? 0 : pa + 1];
-        const uint32_t apred = tour[pa == 0 ? n - 1 : pa - 1];
-        // lane l < k: successor direction, rank l; k <= l < 2k: predecessor, rank l - k
+    // every round sets a bit or shortens the tour; the cap only guards
+    // against a search that would not end
+    const long long max_rounds = 256ll * n + 4096;
+    long long rounds = 0;
+    for (;;) {
+        __syncthreads();
+        const int act = s_active;
+        const int a0 = s_cursor;
+        if (act == 0) break;
+        if (++rounds > max_rounds) {
+            if (t == 0) atomicOr(&vw.state->flags, 16u);
+            return;
+        }
+        const int count = min(C, act);
+
+        // ---- the next `count` active cities from a0, cyclically ----
+        // entry 0: word of a0 from bit a0&31; entries 1..words-1: the following
+        // words; entry `words`: word of a0 below bit a0&31
+        const int w0 = a0 >> 5, b0 = a0 & 31;
+        int found = 0;
+        for (int base = 0; base <= words && found < count; base += nthr) {
+            const int e = base + t;
+            uint32_t bits = 0u;
+            int w = 0;
+            if (e <= words) {
+                uint32_t m;
+                if (e == 0) {
+                    w = w0;
+                    m = 0xFFFFFFFFu << b0;
+                } else if (e < words) {
+                    w = w0 + e;
+                    if (w >= words) w -= words;
+                    m = 0xFFFFFFFFu;
+                } else {
+                    w = w0;
+                    m = b0 ? ((1u << b0) - 1u) : 0u;
+                }
+                if (w == words - 1) m &= lastmask;
+                bits = ~dlb[w] & m;
+            }
+            const int cnt = __popc(bits);
+            const int incl = wave_incl_scan(cnt, lane);
+            if (lane == 63) s_wsum[wave] = incl;
+            __syncthreads();
+            int before = 0, total = 0;
+            for (int q = 0; q < nwaves; ++q) {
+                const int v = s_wsum[q];
+                before += q < wave ? v : 0;
+                total += v;
+            }
+            int idx = found + before + incl - cnt;
+            while (bits && idx < count) {
+                s_list[idx++] = (uint16_t)(w * 32 + __ffs(bits) - 1);
+                bits &= bits - 1u;
+            }
+            found += total;
+            __syncthreads();  // s_wsum reused, s_list complete
+        }
+
+        // ---- evaluate every candidate move of the listed cities ----
+        const int g = t / gs, rl = t % gs;
         bool ok = false;
-        uint32_t c = 0, c1 = 0, a1 = 0;
-        const bool pred_dir = lane >= k;
-        if (lane < 2 * k) {
-            const int r = pred_dir ? lane - k : lane;
-            a1 = pred_dir ? apred : asucc;
+        int a = 0, a1 = 0, c = 0, c1 = 0, dac = 0, da1c1 = 0, pa = 0;
+        const bool pred_dir = rl >= k;
+        if (g < count && rl < 2 * k) {
+            a = s_list[g];
+            const int r = pred_dir ? rl - k : rl;
             c = nn[(size_t)a * k + r];
-            const int64_t g1 = dd(dist, n, a, a1) - (int64_t)nnd[(size_t)a * k + r];
+            dac = nnd[(size_t)a * k + r];
+            pa = pos[a];
+            const int pa_n = pa + 1 == n ? 0 : pa + 1, pa_p = pa == 0 ? n - 1 : pa - 1;
+            a1 = pred_dir ? tour[pa_p] : tour[pa_n];
+            const int32_t daa1 = kLen ? elen[pred_dir ? pa_p : pa] : dist[(size_t)a * n + a1];
+            const int64_t g1 = (int64_t)daa1 - dac;
             if (g1 > 0) {
                 const int pc = pos[c];
-                c1 = pred_dir ? tour[pc == 0 ? n - 1 : pc - 1] : tour[pc + 1 == n ? 0 : pc + 1];
-                if (c != a1 && c1 != (uint32_t)a) {
-                    const int64_t gain = g1 + dd(dist, n, c, c1) - dd(dist, n, a1, c1);
-                    ok = gain > 0;
+                const int pc_n = pc + 1 == n ? 0 : pc + 1, pc_p = pc == 0 ? n - 1 : pc - 1;
+                c1 = pred_dir ? tour[pc_p] : tour[pc_n];
+                if (c != a1 && c1 != a) {
+                    const int32_t dcc1 = kLen ? elen[pred_dir ? pc_p : pc] : dist[(size_t)c * n + c1];
+                    da1c1 = dist[(size_t)a1 * n + c1];
+                    ok = g1 + (int64_t)dcc1 - (int64_t)da1c1 > 0;
                 }
             }
         }
         const uint64_t mask = __ballot(ok);
-        if (mask == 0ull) {
-            if (lane == 0) dlb[a >> 5] |= 1u << (a & 31);
-            active -= 1;
-            a = a + 1 == n ? 0 : a + 1;
-            continue;
+        if (mask != 0ull) {
+            const int m = __ffsll((unsigned long long)mask) - 1;  // lowest lane: first city, first move
+            if (lane == m) {
+                // the two paths the move may reverse; the shorter one (the first on a tie)
+                int i1, j1, i2, j2;
+                if (!pred_dir) {  // a -> a1 ... c -> c1: a1..c or c1..a
+                    i1 = pos[a1];
+                    j1 = pos[c];
+                    i2 = pos[c1];
+                    j2 = pa;
+                } else {          // a1 -> a ... c1 -> c: a..c1 or c..a1
+                    i1 = pa;
+                    j1 = pos[c1];
+                    i2 = pos[c];
+                    j2 = pos[a1];
+                }
+                const int len1 = ((j1 - i1 + n) % n) + 1;
+                const bool first = len1 <= n - len1;
+                s_cand[wave] = Cand{(g << 6) | rl, a, a1, c, c1, first ? i1 : i2, first ? j1 : j2, dac, da1c1};
+            }
+        } else if (lane == 0) {
+            s_cand[wave].key = 0x7FFFFFFF;
         }
-        const int m = __ffsll((unsigned long long)mask) - 1;
-        const bool pdir = m >= k;
-        const uint32_t mc = (uint32_t)__builtin_amdgcn_readlane((int)c, m);
-        const uint32_t mc1 = (uint32_t)__builtin_amdgcn_readlane((int)c1, m);
-        const uint32_t ma1 = pdir ? apred : asucc;
-        int i1, j1, i2, j2;
-        if (!pdir) {  // a -> a1 ... c -> c1: reverse a1..c or c1..a
-            i1 = pos[ma1];
-            j1 = pos[mc];
-            i2 = pos[mc1];
-            j2 = pa;
-        } else {      // a1 -> a ... c1 -> c: reverse a..c1 or c..a1
-            i1 = pa;
-            j1 = pos[mc1];
-            i2 = pos[mc];
-            j2 = pos[ma1];
-        }
-        const int len1 = ((j1 - i1 + n) % n) + 1;
-        if (len1 <= n - len1)
-            reverse_path(tour, pos, n, i1, j1, lane);
-        else
-            reverse_path(tour, pos, n, i2, j2, lane);
-        // clear the bits of the four end points (all lanes read, lane 0 writes)
-        const uint32_t ends[4] = {(uint32_t)a, ma1, mc, mc1};
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const uint32_t x = ends[e];
-            const uint32_t bit = 1u << (x & 31);
-            if (dlb[x >> 5] & bit) {
-                active += 1;
-                if (lane == 0) dlb[x >> 5] &= ~bit;
+        __syncthreads();
+        int best = 0;
+        for (int q = 1; q < nwaves; ++q) best = s_cand[q].key < s_cand[best].key ? q : best;
+        const Cand mv = s_cand[best];
+        const bool moved = mv.key != 0x7FFFFFFF;
+        const int gstar = moved ? (mv.key >> 6) : count;  // cities before it have no move
+        if (t < gstar) atomicOr(&dlb[s_list[t] >> 5], 1u << (s_list[t] & 31));
+        int len = 0;
+        if (moved) {
+            len = ((mv.j - mv.i + n) % n) + 1;
+            for (int q = t; q < len / 2; q += nthr) {
+                int p = mv.i + q;
+                if (p >= n) p -= n;
+                int r = mv.j - q;
+                if (r < 0) r += n;
+                const uint16_t tp = tour[p], tr = tour[r];
+                tour[p] = tr;
+                tour[r] = tp;
+                pos[tr] = (uint16_t)p;
+                pos[tp] = (uint16_t)r;
+            }
+            if (kLen) {  // the edges inside the path keep their lengths, in reverse order
+                for (int q = t; q < (len - 1) / 2; q += nthr) {
+                    int p = mv.i + q;
+                    if (p >= n) p -= n;
+                    int r = mv.j - 1 - q;
+                    if (r < 0) r += n;
+                    const int32_t ep = elen[p], er = elen[r];
+                    elen[p] = er;
+                    elen[r] = ep;
+                }
             }
         }
+        __syncthreads();
+        if (t == 0) {
+            int active = act - gstar;
+            if (moved) {
+                if (kLen) {  // the two new edges close the reversed path
+                    const int pl = mv.i == 0 ? n - 1 : mv.i - 1;
+                    const int x = tour[pl];
+                    const bool left_ac = x == mv.a || x == mv.c;
+                    elen[pl] = left_ac ? mv.dac : mv.da1c1;
+                    elen[mv.j] = left_ac ? mv.da1c1 : mv.dac;
+                }
+                const int ends[4] = {mv.a, mv.a1, mv.c, mv.c1};
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t bit = 1u << (ends[e] & 31);
+                    if (dlb[ends[e] >> 5] & bit) {
+                        dlb[ends[e] >> 5] &= ~bit;
+                        active += 1;
+                    }
+                }
+                s_cursor = mv.a;
+            } else {
+                const int last = s_list[count - 1];
+                s_cursor = last + 1 == n ? 0 : last + 1;
+            }
+            s_active = active;
+        }
     }
-    int64_t len = 0;
-    for (int i = lane; i < n; i += kWave) {
-        const uint16_t t = tour[i];
-        gtour[i] = t;
-        len += dd(dist, n, t, tour[i + 1 == n ? 0 : i + 1]);
+    // write back; the tour length from the final edges
+    int64_t tl = 0;
+    for (int i = t; i < n; i += nthr) {
+        const uint16_t v = tour[i];
+        gtour[i] = v;
+        tl += kLen ? (int64_t)elen[i] : (int64_t)dist[(size_t)v * n + tour[i + 1 == n ? 0 : i + 1]];
     }
-    len = wave_sum_i64(len);
-    if (lane == 0) vw.lengths[ant] = len;
+    tl = wave_sum_i64(tl);
+    if (lane == 0) atomicAdd(&s_len, (unsigned long long)tl);
+    __syncthreads();
+    if (t == 0) vw.lengths[ant] = (int64_t)s_len;
 }
 
 // d(i, nn[i][r]) for the 2-opt neighbour lists
@@ -178,8 +293,10 @@ __global__ __launch_bounds__(256) void k_nn_dist(const int32_t* __restrict__ dis
 
 }  // namespace
 
-size_t two_opt_lds_bytes(const Shape& s) {
-    return (size_t)((4 * s.n + 15) & ~15) + 4 * (size_t)((s.n + 31) / 32);
+// dynamic LDS of the 2-opt kernel: tour and position (uint16), the edge
+// lengths (int32) when `with_len`, and the don't-look bits
+size_t two_opt_lds_bytes(const Shape& s, bool with_len) {
+    return (size_t)((4 * s.n + 15) & ~15) + (with_len ? 4 * (size_t)s.n : 0) + 4 * (size_t)((s.n + 31) / 32);
 }
 
 hipError_t launch_two_opt_prepare(const Views& v, const Shape& s, int32_t* nnd, hipStream_t st) {
@@ -192,13 +309,17 @@ hipError_t launch_two_opt_prepare(const Views& v, const Shape& s, int32_t* nnd, 
 }
 
 hipError_t launch_two_opt(const Views& v, const Shape& s, const int32_t* nnd, hipStream_t st) {
-    const size_t lds = two_opt_lds_bytes(s);
+    const bool with_len = two_opt_lds_bytes(s, true) + kTwoOptStaticLds <= (size_t)max_lds_per_block();
+    const size_t lds = two_opt_lds_bytes(s, with_len);
+    const void* kern = with_len ? (const void*)k_two_opt<true> : (const void*)k_two_opt<false>;
     if (lds > 64 * 1024) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_two_opt, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    k_two_opt<<<s.ants, 64, lds, st>>>(v, s, nnd);
-    return hipGetLastError();
+    Views vv = v;
+    Shape ss = s;
+    void* args[] = {(void*)&vv, (void*)&ss, (void*)&nnd};
+    return hipLaunchKernel(kern, dim3(s.ants), dim3(64 * s.two_opt_waves), args, lds, st);
 }
 
 }  // namespace mmas

@@ -55,7 +55,7 @@ EXPORTED = (
     "mmas_batch_capture", "mmas_batch_step", "mmas_batch_iteration", "mmas_batch_context",
     "mmas_batch_destroy", "mmas_mlp_param_count", "mmas_mlp_packed_count", "mmas_mlp_features",
     "mmas_mlp_pack", "mmas_mlp_forward", "mmas_mlp_grad", "mmas_mlp_adam", "mmas_mlp_labels",
-    "mmas_set_learned_heuristic", "mmas_last_error",
+    "mmas_set_learned_heuristic", "mmas_last_error", "mmas_set_two_opt_launch",
 )
 
 
@@ -90,6 +90,10 @@ def _load():
         raise ImportError(
             f"{LIB_PATH} is not built; build it with paper_2003_11902_amd/build.py "
             "(or __graft_entry__.build())")
+    # torch first: its HIP runtime (libamdhip64.so.7) is then the one the
+    # library binds to. Loaded the other way round, torch brings a second HIP
+    # and HSA runtime into the process and one of them sees no device.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     p = C.c_void_p
     L.mmas_workspace_bytes.argtypes = [C.POINTER(mmas_params)]
@@ -99,8 +103,10 @@ def _load():
     for name in ("mmas_prepare_choice_info", "mmas_two_opt", "mmas_update_pheromone", "mmas_synchronize"):
         getattr(L, name).argtypes = [p]
         getattr(L, name).restype = C.c_int
-    L.mmas_set_launch.argtypes = [p, C.c_int32, C.c_int32]
+    L.mmas_set_launch.argtypes = [p, C.c_int32, C.c_int32, C.c_int32]
     L.mmas_set_launch.restype = C.c_int
+    L.mmas_set_two_opt_launch.argtypes = [p, C.c_int32]
+    L.mmas_set_two_opt_launch.restype = C.c_int
     L.mmas_construct.argtypes = [p, C.c_uint32]
     L.mmas_construct.restype = C.c_int
     L.mmas_best.argtypes = [p, p, C.POINTER(C.c_int64)]
@@ -121,9 +127,9 @@ def _load():
     L.mmas_batch_workspace_bytes.restype = C.c_int
     L.mmas_batch_create.argtypes = [C.c_int32, p, p, p, C.c_size_t, p, C.POINTER(p)]
     L.mmas_batch_create.restype = C.c_int
-    L.mmas_batch_set_launch.argtypes = [p, C.c_int32, C.c_int32]
+    L.mmas_batch_set_launch.argtypes = [p, C.c_int32, C.c_int32, C.c_int32]
     L.mmas_batch_set_launch.restype = C.c_int
-    L.mmas_batch_tune.argtypes = [p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.mmas_batch_tune.argtypes = [p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.mmas_batch_tune.restype = C.c_int
     for name in ("mmas_batch_capture", "mmas_batch_step"):
         getattr(L, name).argtypes = [p]
@@ -257,11 +263,14 @@ class Colony:
     def construct(self, iteration: int):
         _check(lib.mmas_construct(self._ctx, iteration), "mmas_construct")
 
-    def set_launch(self, ants_per_block=0, table_rows=-1):
-        _check(lib.mmas_set_launch(self._ctx, ants_per_block, table_rows), "mmas_set_launch")
+    def set_launch(self, ants_per_block=0, table_rows=-1, lanes_per_ant=64):
+        _check(lib.mmas_set_launch(self._ctx, ants_per_block, table_rows, lanes_per_ant), "mmas_set_launch")
 
     def two_opt(self):
         _check(lib.mmas_two_opt(self._ctx), "mmas_two_opt")
+
+    def set_two_opt_launch(self, waves_per_ant=0):
+        _check(lib.mmas_set_two_opt_launch(self._ctx, waves_per_ant), "mmas_set_two_opt_launch")
 
     def update_pheromone(self):
         _check(lib.mmas_update_pheromone(self._ctx), "mmas_update_pheromone")
@@ -406,14 +415,16 @@ class Batch:
         except Exception:
             pass
 
-    def set_launch(self, ants_per_block=4, table_bytes=-1):
-        _check(lib.mmas_batch_set_launch(self._h, ants_per_block, table_bytes), "mmas_batch_set_launch")
+    def set_launch(self, ants_per_block=4, table_bytes=-1, lanes_per_ant=64):
+        _check(lib.mmas_batch_set_launch(self._h, ants_per_block, table_bytes, lanes_per_ant), "mmas_batch_set_launch")
 
     def tune(self):
+        """(ants_per_block, table_bytes, lanes_per_ant) chosen by the autotuner."""
         apb = C.c_int32()
         tb = C.c_int32()
-        _check(lib.mmas_batch_tune(self._h, C.byref(apb), C.byref(tb)), "mmas_batch_tune")
-        return int(apb.value), int(tb.value)
+        lanes = C.c_int32()
+        _check(lib.mmas_batch_tune(self._h, C.byref(apb), C.byref(tb), C.byref(lanes)), "mmas_batch_tune")
+        return int(apb.value), int(tb.value), int(lanes.value)
 
     def capture(self):
         _check(lib.mmas_batch_capture(self._h), "mmas_batch_capture")

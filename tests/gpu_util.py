@@ -55,8 +55,11 @@ def compare_iteration(g, o, it, check_tau=True):
     return True
 
 
-def run_parity(dist, iterations, nthreads=8, **kw):
+def run_parity(dist, iterations, nthreads=8, launch=None, **kw):
+    """`launch` = (ants_per_block, table_rows, lanes_per_ant) for the GPU side."""
     g, o = make_pair(dist, **kw)
+    if launch is not None:
+        g.set_launch(*launch)
     identical = True
     for it in range(iterations):
         g.iterate(it)

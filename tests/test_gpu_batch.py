@@ -43,7 +43,7 @@ def singles(dists, params, iterations):
         hist = []
         for it in range(iterations):
             c.iterate(it)
-            hist.append((c.tours().copy(), c.pheromone().copy()))
+            hist.append((c.tours().copy(), c.pheromone().copy(), c.lengths().copy()))
         out.append(hist)
     return out
 
@@ -69,18 +69,21 @@ def test_launch_shapes_and_tuner_do_not_change_results(gpu):
     from paper_2003_11902_amd import mmas as M
     dists, params = small_batch(count=6, seed=400)
     ref = singles(dists, params, 2)
-    for apb, tb in [(1, -1), (2, 0), (8, -1), (16, 0), (16, 4096)]:
-        say(f"shape {apb} {tb}")
+    shapes = [(1, -1, 64), (2, 0, 64), (8, -1, 64), (16, 0, 64), (16, 4096, 64),
+              (2, -1, 32), (4, 0, 32), (8, -1, 32), (16, 4096, 32)]
+    for apb, tb, lanes in shapes:
+        say(f"shape {apb} {tb} {lanes}")
         b = M.Batch(dists, params)
-        b.set_launch(apb, tb)
+        b.set_launch(apb, tb, lanes)
         for it in range(2):
             b.step()
         b.synchronize()
         for i in range(len(dists)):
-            assert np.array_equal(b.instance(i).tours(), ref[i][1][0]), (apb, tb, i)
+            assert np.array_equal(b.instance(i).tours(), ref[i][1][0]), (apb, tb, lanes, i)
+            assert np.array_equal(b.instance(i).lengths(), ref[i][1][2]), (apb, tb, lanes, i)
     b = M.Batch(dists, params)
-    apb, tb = b.tune()
-    assert apb in (4, 8, 16)
+    apb, tb, lanes = b.tune()
+    assert apb in (4, 8, 16) and lanes in (32, 64)
     b.step()
     b.step()
     b.synchronize()

@@ -188,3 +188,22 @@ def test_error_paths(gpu):
     g.iterate(0)
     t, length = g.best()
     assert length > 0 and sorted(t.tolist()) == list(range(50))
+
+
+@pytest.mark.parametrize("launch,tabu,pher,cl,ants", [
+    ((1, 0, 64), "bitmask", "dense", 32, 101),
+    ((8, -1, 64), "compact", "dense", 32, 101),
+    ((16, 50, 64), "bitmask", "candidates", 20, 64),
+    ((2, -1, 32), "bitmask", "dense", 32, 101),
+    ((4, 0, 32), "compact", "dense", 32, 101),
+    ((8, 60, 32), "bitmask", "candidates", 16, 64),
+    ((16, -1, 32), "compact", "candidates", 7, 33),
+    ((4, -1, 32), "bitmask", "dense", 0, 20),  # no list: 32 lanes fall back to one ant per wave
+])
+def test_launch_shapes_match_oracle(gpu, launch, tabu, pher, cl, ants):
+    """Ants per workgroup, LDS table rows and two ants per wave (32 lanes
+    each) never change tours, lengths, fallback counts or trails; odd ant
+    counts leave the last wave with one ant."""
+    _, d = I.make_instance("clustered", 230, seed=77, clusters=5, sigma=500.0)
+    say(f"launch {launch} {tabu} {pher} cl={cl} ants={ants}")
+    run_parity(d, 3, launch=launch, ants=ants, cand_len=cl, rho=0.05, seed=9, tabu=tabu, pher=pher)
