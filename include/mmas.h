@@ -300,8 +300,10 @@ mmas_status mmas_mlp_labels(const uint16_t* tours_dev, int32_t tours, int32_t n,
 
 /* Installs the learned heuristic in a context: eta^beta with
  * eta_ij = fl(fl(1/d_ij) * fl(2 sigmoid(s_ij))) on the kNN edges (score_dev:
- * n*16 floats by edge 16 i + r, knn_dev: n*16), 1/d elsewhere; sigmoid uses
- * the library's FP32 exp. Marks choice_info stale. n >= 17. */
+ * n*16 floats by edge 16 i + r, knn_dev: n*16); every other edge of i takes
+ * the multiplier of i's lowest score, fl(2 sigmoid(min_r s_ir)), so all-zero
+ * scores give the plain eta = 1/d; sigmoid uses the library's FP32 exp.
+ * Marks choice_info stale. n >= 17. */
 mmas_status mmas_set_learned_heuristic(mmas_ctx* ctx, const uint16_t* knn_dev, const float* score_dev);
 
 /* Diagnostics, for checking the device arithmetic against an independent

@@ -244,25 +244,33 @@ float orc_expf(float x) {
     return ldexpf(p, (int)kf);
 }
 
-/* eta_ij = fl(fl(1/d_ij) * fl(2 * sigma(s_ij))) on the 16 nearest of i,
- * sigma(s) = 1 / (1 + orc_expf(-s)); eta = 1/d elsewhere; heur = eta^beta
- * (left-to-right products); heur_ii = 0. s: n*16 by edge 16 i + r. */
+/* eta_ij = fl(fl(1/d_ij) * fl(2 * sigma(s_ij))) on the 16 nearest of i;
+ * every other edge of i takes the multiplier of i's lowest-scored edge,
+ * fl(2 * sigma(min_r s_ir)) (an unscored edge counts as no better than the
+ * worst scored one); sigma(s) = 1 / (1 + orc_expf(-s)); heur = eta^beta
+ * (left-to-right products); heur_ii = 0. s: n*16 by edge 16 i + r. With
+ * all scores 0 every multiplier is 1 and heur is the plain eta^beta. */
 void orc_install_eta(int n, const int32_t* dist, const uint16_t* knn, const float* s, int beta, float* heur) {
-    for (int i = 0; i < n; ++i)
+    for (int i = 0; i < n; ++i) {
+        float smin = s[i * 16];
+        for (int r = 1; r < 16; ++r)
+            if (s[i * 16 + r] < smin) smin = s[i * 16 + r];
         for (int j = 0; j < n; ++j) {
             float h = 0.0f;
             if (i != j) {
                 const float eta = 1.0f / (float)dist[(size_t)i * n + j];
-                float x = eta;
+                float sc = smin;
                 for (int r = 0; r < 16; ++r)
                     if (knn[i * 16 + r] == j) {
-                        const float sg = 1.0f / (1.0f + orc_expf(-s[i * 16 + r]));
-                        x = eta * (2.0f * sg);
+                        sc = s[i * 16 + r];
                         break;
                     }
+                const float sg = 1.0f / (1.0f + orc_expf(-sc));
+                const float x = eta * (2.0f * sg);
                 h = 1.0f;
                 for (int b = 0; b < beta; ++b) h = h * x;
             }
             heur[(size_t)i * n + j] = h;
         }
+    }
 }

@@ -3,7 +3,8 @@
 // edge-scoring MLP in bfloat16 on MFMA with FP32 accumulation (inference,
 // and training by binary cross-entropy with logits and Adam), and the
 // installation eta_ij = (1/d_ij) * 2 sigmoid(s_ij) on the 16 nearest cities
-// of i (eta = 1/d elsewhere, so s = 0 gives the plain heuristic exactly).
+// of i; the other edges of i take the multiplier of i's lowest score, so
+// s = 0 gives the plain heuristic exactly.
 //
 // MFMA: v_mfma_f32_16x16x16_bf16. With lane l, row block q = l / 16 and
 // column c = l % 16: the A operand of lane l is A[c][4q .. 4q+3] (row c,
@@ -447,12 +448,18 @@ __global__ __launch_bounds__(256) void k_install(const int32_t* __restrict__ dis
         float h = 0.0f;
         if (i != j) {
             const float eta = 1.0f / (float)dist[(size_t)i * n + j];
-            float x = eta;
-            for (int r = 0; r < kK; ++r)
-                if (knn[i * kK + r] == j) {
-                    x = eta * (2.0f * sigmoid_f32(s[i * kK + r]));
-                    break;
+            // own score if j is among the 16 nearest, else the lowest score of i
+            float smin = s[i * kK], sc = 0.0f;
+            bool found = false;
+            for (int r = 0; r < kK; ++r) {
+                const float v = s[i * kK + r];
+                smin = v < smin ? v : smin;
+                if (!found && knn[i * kK + r] == j) {
+                    sc = v;
+                    found = true;
                 }
+            }
+            const float x = eta * (2.0f * sigmoid_f32(found ? sc : smin));
             h = powi(x, beta);
         }
         heur[e] = h;

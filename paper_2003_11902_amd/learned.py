@@ -141,10 +141,12 @@ def scores(params, dist, xy):
 
 
 def time_to_gap(params, dist, xy, seeds=range(1, 11), budget=500, ants=None, cand_len=32, rho=0.02, check_every=5,
-                log=print):
+                full=True, log=print):
     """Per seed: plain MMAS for `budget` iterations (final best L and wall time
     T); the learned run (inference and installation included) timed until its
-    best first reaches L. Returns a list of dicts."""
+    best first reaches L. With `full`, the learned run then continues (untimed)
+    to `budget` iterations so that both final lengths can be compared.
+    Returns a list of dicts."""
     import torch
 
     n = dist.shape[0]
@@ -164,20 +166,28 @@ def time_to_gap(params, dist, xy, seeds=range(1, 11), budget=500, ants=None, can
         knn, s = scores(params, dist, xy)
         learned.set_learned_heuristic(knn, s)
         reached = None
+        t_star = None
         L_learned = None
-        for it in range(budget):
+        it = 0
+        while it < budget:
             learned.iterate(it)
-            if (it + 1) % check_every == 0 or it == budget - 1:
+            it += 1
+            if reached is None and (it % check_every == 0 or it == budget):
                 _, L_learned = learned.best()
                 if L_learned <= L_plain:
-                    reached = it + 1
-                    break
-        t_star = time.perf_counter() - t1
-        rec = {"seed": seed, "plain_len": L_plain, "plain_s": T_plain, "learned_len": L_learned,
-               "learned_iters": reached, "learned_s": t_star,
+                    reached = it
+                    t_star = time.perf_counter() - t1
+                    if not full:
+                        break
+        _, L_final = learned.best()
+        if t_star is None:
+            t_star = time.perf_counter() - t1
+        rec = {"seed": seed, "plain_len": L_plain, "plain_s": T_plain, "learned_iters": reached, "learned_s": t_star,
+               "learned_final_len": L_final if full else None, "learned_final_iters": it,
                "ratio": (t_star / T_plain) if reached is not None else None}
         log(f"[learned] seed {seed}: plain {L_plain} in {T_plain:.2f} s; learned "
-            f"{'reached at ' + str(reached) if reached else 'did not reach'} in {t_star:.2f} s")
+            f"{'reached it at iteration ' + str(reached) if reached else 'did not reach it'} in {t_star:.2f} s"
+            + (f"; learned after {it} iterations: {L_final}" if full else ""))
         out.append(rec)
         plain.close()
         learned.close()
@@ -201,7 +211,9 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--eval-n", type=int, default=3795)
     ap.add_argument("--eval-seeds", type=int, default=10)
-    ap.add_argument("--budget", type=int, default=500)
+    ap.add_argument("--budget", type=int, default=1000)
+    ap.add_argument("--eval-cand-len", type=int, default=32,
+                    help="candidate-list length of both evaluated runs")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
@@ -213,10 +225,11 @@ def main(argv=None):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     xy, dist = I.make_instance("uniform", args.eval_n, seed=5)
-    recs = time_to_gap(params, dist, xy, seeds=range(1, args.eval_seeds + 1), budget=args.budget)
+    recs = time_to_gap(params, dist, xy, seeds=range(1, args.eval_seeds + 1), budget=args.budget,
+                       cand_len=args.eval_cand_len)
     ratios = [r["ratio"] for r in recs if r["ratio"] is not None]
     out = {"metric": "time-to-gap learned vs plain", "eval_instance": f"uniform n={args.eval_n} seed 5",
-           "budget_iterations": args.budget, "reached": len(ratios), "seeds": len(recs),
+           "budget_iterations": args.budget, "eval_cand_len": args.eval_cand_len, "reached": len(ratios), "seeds": len(recs),
            "median_ratio": float(np.median(ratios)) if ratios else None,
            "train_edges": int(X.shape[0]), "train_instances": args.count, "data_s": t_data,
            "train_s": t_train, "loss": hist, "runs": recs}

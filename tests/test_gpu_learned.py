@@ -178,3 +178,20 @@ def test_pipeline_small(gpu):
     xy, d = I.make_instance("uniform", 200, seed=3)
     recs = L.time_to_gap(params, d, xy, seeds=[1], budget=20, ants=64, log=say)
     assert len(recs) == 1 and recs[0]["plain_len"] > 0
+
+
+def test_learned_heuristic_reaches_plain_quality_sooner(gpu):
+    """The gain of the trained network: trained on small generated instances
+    (n 200-400), installed on an unseen 800-city instance, MMAS with the
+    learned eta reaches the tour length plain MMAS has after 150 iterations
+    in fewer than half as many iterations (deterministic: seeded data,
+    fixed-order reductions)."""
+    from paper_2003_11902_amd import learned as L
+    say("learned gain: 64 training instances, eval n=800, budget 150")
+    X, F = L.training_set(count=64, n_lo=200, n_hi=400, base_seed=4242, R=2, iterations=40, ants=64, log=say)
+    params, hist = L.train(X, F, epochs=6, batch=8192, log=say)
+    assert hist[-1] < hist[0]
+    xy, d = I.make_instance("uniform", 800, seed=99)
+    recs = L.time_to_gap(params, d, xy, seeds=[1, 2], budget=150, ants=200, log=say)
+    for r in recs:
+        assert r["learned_iters"] is not None and r["learned_iters"] < 75, r

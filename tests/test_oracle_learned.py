@@ -140,7 +140,17 @@ def test_install_identity_and_scaling(orc):
     i, r = 5, 3
     j = knn[i, r]
     assert math.isclose(h[i, j], (1 / d[i, j]) * 2 / (1 + math.exp(-s[i, r])), rel_tol=3e-7)
+    # an unscored edge takes the multiplier of its row's lowest score
     mask = np.ones((120, 120), bool)
     mask[np.arange(120)[:, None], knn] = False
     np.fill_diagonal(mask, False)
-    assert np.allclose(h[mask], 1.0 / d[mask], rtol=1e-7)
+    smin = s.astype(np.float64).min(axis=1)
+    dd = np.where(np.eye(120, dtype=bool), 1, d).astype(np.float64)  # the diagonal is excluded below
+    want = (1.0 / dd) * (2.0 / (1.0 + np.exp(-smin)))[:, None]
+    assert np.allclose(h[mask], want[mask], rtol=1e-6)
+    # the unscored multiplier h*d of a row is the smallest scored one
+    mult = h * dd
+    rows = np.arange(120)
+    scored_min = mult[rows[:, None], knn].min(axis=1)
+    for i in (0, 17, 119):
+        assert np.allclose(mult[i][mask[i]], scored_min[i], rtol=1e-6)
