@@ -28,10 +28,12 @@ constexpr int kMaxWaves = 16;
 constexpr int kMaxList = 512;  // cities examined per round (1024 threads / groups of >= 2)
 
 struct Cand {
-    int key;                 // (list index << 6) | lane in group; INT_MAX if none
+    int key;                 // (list index << 6) | lane in group
     int a, a1, c, c1;
     int i, j;                // cyclic position range to reverse
     int dac, da1c1;          // lengths of the two new edges
+    int flags;               // bits 0-3: don't-look bit of a, a1, c, c1 before the round;
+                             // bit 4: the edge left of position i becomes {a, c}
 };
 
 // Inclusive prefix sum over the wave: row scans by DPP, row totals by readlane.
@@ -48,6 +50,8 @@ __device__ __forceinline__ int wave_incl_scan(int x, int lane) {
     return x;
 }
 
+__device__ __forceinline__ uint32_t dlb_bit(const uint32_t* dlb, int x) { return (dlb[x >> 5] >> (x & 31)) & 1u; }
+
 // The 2-opt of one ant per workgroup. kLen: the tour's edge lengths are kept
 // in LDS by position (len[p] = d(tour[p], tour[p+1])), so a move evaluation
 // reads one distance from HBM instead of three.
@@ -57,14 +61,14 @@ __device__ __forceinline__ int wave_incl_scan(int x, int lane) {
 // The first of them (in that order) with an improving move is the city the
 // sequential search reaches next with a move: the cities before it have none
 // and get their bits set, its move is applied and it is examined again. With
-// no move among the C, all C get their bits set.
+// no move among the C, all C get their bits set. The number of active cities
+// and the cursor are kept by every thread alike (no broadcast needed).
 template <bool kLen>
 __global__ __launch_bounds__(1024) void k_two_opt(Views vw, Shape s, const int32_t* __restrict__ nnd) {
     extern __shared__ __align__(16) uint8_t smem[];
-    __shared__ uint16_t s_list[kMaxList];
-    __shared__ int s_wsum[kMaxWaves];
+    __shared__ uint16_t s_lists[2][kMaxList];  // by round parity
     __shared__ Cand s_cand[kMaxWaves];
-    __shared__ int s_active, s_cursor;
+    __shared__ int s_key[kMaxWaves];
     __shared__ unsigned long long s_len;
     const int n = s.n, k = s.ls_nn;
     const int ant = blockIdx.x;
@@ -92,91 +96,89 @@ __global__ __launch_bounds__(1024) void k_two_opt(Views vw, Shape s, const int32
         pos[v] = (uint16_t)i;
     }
     for (int w = t; w < words; w += nthr) dlb[w] = 0u;
-    if (t == 0) {
-        s_active = n;
-        s_cursor = 0;
-        s_len = 0ull;
-    }
+    if (t == 0) s_len = 0ull;
     __syncthreads();
     if (kLen)
         for (int i = t; i < n; i += nthr) elen[i] = dist[(size_t)tour[i] * n + tour[i + 1 == n ? 0 : i + 1]];
 
+    int act = n, a0 = 0;  // active cities and cursor (the same in every thread)
+    int ca = -1, cc = 0, cdac = 0;  // this lane's last (city, neighbour, distance) from the lists
     // every round sets a bit or shortens the tour; the cap only guards
     // against a search that would not end
     const long long max_rounds = 256ll * n + 4096;
     long long rounds = 0;
-    for (;;) {
-        __syncthreads();
-        const int act = s_active;
-        const int a0 = s_cursor;
-        if (act == 0) break;
+    while (act > 0) {
         if (++rounds > max_rounds) {
             if (t == 0) atomicOr(&vw.state->flags, 16u);
             return;
         }
         const int count = min(C, act);
+        // Only wave 0 writes the bits (below), so it may list the next cities
+        // at once; the other waves' last reversal is ordered before this
+        // round's evaluation by the barrier after the list.
+        uint16_t* s_list = s_lists[rounds & 1];
 
         // ---- the next `count` active cities from a0, cyclically ----
-        // entry 0: word of a0 from bit a0&31; entries 1..words-1: the following
-        // words; entry `words`: word of a0 below bit a0&31
-        const int w0 = a0 >> 5, b0 = a0 & 31;
-        int found = 0;
-        for (int base = 0; base <= words && found < count; base += nthr) {
-            const int e = base + t;
-            uint32_t bits = 0u;
-            int w = 0;
-            if (e <= words) {
-                uint32_t m;
-                if (e == 0) {
-                    w = w0;
-                    m = 0xFFFFFFFFu << b0;
-                } else if (e < words) {
-                    w = w0 + e;
-                    if (w >= words) w -= words;
-                    m = 0xFFFFFFFFu;
-                } else {
-                    w = w0;
-                    m = b0 ? ((1u << b0) - 1u) : 0u;
+        // (wave 0 alone) entries in order: the word of a0 from bit a0&31, the
+        // following words, the word of a0 below bit a0&31; 64 words a pass,
+        // until `count` cities are listed
+        if (wave == 0) {
+            const int w0 = a0 >> 5, b0 = a0 & 31;
+            int found = 0;
+            for (int base = 0; base <= words && found < count; base += kWave) {
+                const int e = base + lane;
+                uint32_t bits = 0u;
+                int w = 0;
+                if (e <= words) {
+                    uint32_t m;
+                    if (e == 0) {
+                        w = w0;
+                        m = 0xFFFFFFFFu << b0;
+                    } else if (e < words) {
+                        w = w0 + e;
+                        if (w >= words) w -= words;
+                        m = 0xFFFFFFFFu;
+                    } else {
+                        w = w0;
+                        m = b0 ? ((1u << b0) - 1u) : 0u;
+                    }
+                    if (w == words - 1) m &= lastmask;
+                    bits = ~dlb[w] & m;
                 }
-                if (w == words - 1) m &= lastmask;
-                bits = ~dlb[w] & m;
+                const int cnt = __popc(bits);
+                const int incl = wave_incl_scan(cnt, lane);
+                int idx = found + incl - cnt;
+                while (bits && idx < count) {
+                    s_list[idx++] = (uint16_t)(w * 32 + __ffs(bits) - 1);
+                    bits &= bits - 1u;
+                }
+                found += __builtin_amdgcn_readlane(incl, 63);
             }
-            const int cnt = __popc(bits);
-            const int incl = wave_incl_scan(cnt, lane);
-            if (lane == 63) s_wsum[wave] = incl;
-            __syncthreads();
-            int before = 0, total = 0;
-            for (int q = 0; q < nwaves; ++q) {
-                const int v = s_wsum[q];
-                before += q < wave ? v : 0;
-                total += v;
-            }
-            int idx = found + before + incl - cnt;
-            while (bits && idx < count) {
-                s_list[idx++] = (uint16_t)(w * 32 + __ffs(bits) - 1);
-                bits &= bits - 1u;
-            }
-            found += total;
-            __syncthreads();  // s_wsum reused, s_list complete
         }
+        __syncthreads();  // s_list complete
 
         // ---- evaluate every candidate move of the listed cities ----
         const int g = t / gs, rl = t % gs;
         bool ok = false;
-        int a = 0, a1 = 0, c = 0, c1 = 0, dac = 0, da1c1 = 0, pa = 0;
+        int a = 0, a1 = 0, c = 0, c1 = 0, dac = 0, da1c1 = 0, pa = 0, pc = 0;
         const bool pred_dir = rl >= k;
         if (g < count && rl < 2 * k) {
             a = s_list[g];
             const int r = pred_dir ? rl - k : rl;
-            c = nn[(size_t)a * k + r];
-            dac = nnd[(size_t)a * k + r];
+            if (a != ca) {  // the list often starts where the last one did
+                cc = nn[(size_t)a * k + r];
+                cdac = nnd[(size_t)a * k + r];
+                ca = a;
+            }
+            c = cc;
+            dac = cdac;
             pa = pos[a];
             const int pa_n = pa + 1 == n ? 0 : pa + 1, pa_p = pa == 0 ? n - 1 : pa - 1;
             a1 = pred_dir ? tour[pa_p] : tour[pa_n];
             const int32_t daa1 = kLen ? elen[pred_dir ? pa_p : pa] : dist[(size_t)a * n + a1];
             const int64_t g1 = (int64_t)daa1 - dac;
             if (g1 > 0) {
-                const int pc = pos[c];
+                pc = pos[c];
                 const int pc_n = pc + 1 == n ? 0 : pc + 1, pc_p = pc == 0 ? n - 1 : pc - 1;
                 c1 = pred_dir ? tour[pc_p] : tour[pc_n];
                 if (c != a1 && c1 != a) {
@@ -190,86 +192,113 @@ __global__ __launch_bounds__(1024) void k_two_opt(Views vw, Shape s, const int32
         if (mask != 0ull) {
             const int m = __ffsll((unsigned long long)mask) - 1;  // lowest lane: first city, first move
             if (lane == m) {
-                // the two paths the move may reverse; the shorter one (the first on a tie)
+                // the two paths the move may reverse (positions from pa and pc:
+                // a1 and c1 sit next to a and c); the shorter one, the first on a tie
+                const int pa_n = pa + 1 == n ? 0 : pa + 1, pa_p = pa == 0 ? n - 1 : pa - 1;
+                const int pc_n = pc + 1 == n ? 0 : pc + 1, pc_p = pc == 0 ? n - 1 : pc - 1;
                 int i1, j1, i2, j2;
                 if (!pred_dir) {  // a -> a1 ... c -> c1: a1..c or c1..a
-                    i1 = pos[a1];
-                    j1 = pos[c];
-                    i2 = pos[c1];
+                    i1 = pa_n;
+                    j1 = pc;
+                    i2 = pc_n;
                     j2 = pa;
                 } else {          // a1 -> a ... c1 -> c: a..c1 or c..a1
                     i1 = pa;
-                    j1 = pos[c1];
-                    i2 = pos[c];
-                    j2 = pos[a1];
+                    j1 = pc_p;
+                    i2 = pc;
+                    j2 = pa_p;
                 }
-                const int len1 = ((j1 - i1 + n) % n) + 1;
+                int len1 = j1 - i1;
+                if (len1 < 0) len1 += n;
+                len1 += 1;
                 const bool first = len1 <= n - len1;
-                s_cand[wave] = Cand{(g << 6) | rl, a, a1, c, c1, first ? i1 : i2, first ? j1 : j2, dac, da1c1};
+                const int i = first ? i1 : i2, j = first ? j1 : j2;
+                const int x = tour[i == 0 ? n - 1 : i - 1];  // stays left of the reversed path
+                const int fl = (int)dlb_bit(dlb, a) | ((int)dlb_bit(dlb, a1) << 1) | ((int)dlb_bit(dlb, c) << 2) |
+                               ((int)dlb_bit(dlb, c1) << 3) | ((x == a || x == c) ? 16 : 0);
+                s_cand[wave] = Cand{(g << 6) | rl, a, a1, c, c1, i, j, dac, da1c1, fl};
+                s_key[wave] = (g << 6) | rl;
             }
         } else if (lane == 0) {
-            s_cand[wave].key = 0x7FFFFFFF;
+            s_key[wave] = 0x7FFFFFFF;
         }
         __syncthreads();
-        int best = 0;
-        for (int q = 1; q < nwaves; ++q) best = s_cand[q].key < s_cand[best].key ? q : best;
-        const Cand mv = s_cand[best];
-        const bool moved = mv.key != 0x7FFFFFFF;
-        const int gstar = moved ? (mv.key >> 6) : count;  // cities before it have no move
-        if (t < gstar) atomicOr(&dlb[s_list[t] >> 5], 1u << (s_list[t] & 31));
-        int len = 0;
+        // the first move over all waves: keys are (list index, lane), distinct
+        const uint32_t kk = lane < nwaves ? (uint32_t)s_key[lane] : 0x7FFFFFFFu;
+        const uint32_t kmin = wave_min_u32<2>(kk);  // lanes 0-31 (kMaxWaves <= 32)
+        const int best = __ffsll((unsigned long long)__ballot(kk == kmin)) - 1;
+        const bool moved = kmin != 0x7FFFFFFFu;
+        Cand mv{};
+        if (moved) mv = s_cand[best];
+        const int gstar = moved ? (mv.key >> 6) : count;  // the listed cities before it have no move
+        const int last = s_list[count - 1];
+        // the listed cities before the move's city get their bits set, except
+        // the move's end points, whose bits end clear (wave 0 only)
+        if (wave == 0)
+            for (int q = lane; q < gstar; q += kWave) {
+                const int x = s_list[q];
+                if (!moved || (x != mv.a1 && x != mv.c && x != mv.c1))
+                    atomicOr(&dlb[x >> 5], 1u << (x & 31));
+            }
+        int newact = act - gstar;
         if (moved) {
-            len = ((mv.j - mv.i + n) % n) + 1;
-            for (int q = t; q < len / 2; q += nthr) {
+            // an end point's bit is set after the listing if it was set before
+            // the round or if it lies in the listed part before the move's city
+            int span = mv.a - a0;
+            if (span < 0) span += n;
+            const int ends[4] = {mv.a, mv.a1, mv.c, mv.c1};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                int de = ends[e] - a0;
+                if (de < 0) de += n;
+                const bool was = ((mv.flags >> e) & 1) || (e > 0 && de < span);
+                newact += was ? 1 : 0;
+            }
+            if (t < 4 && ((mv.flags >> t) & 1)) atomicAnd(&dlb[ends[t] >> 5], ~(1u << (ends[t] & 31)));  // wave 0
+            // reverse positions i..j of the tour and i..j-1 of the edge lengths
+            int len = mv.j - mv.i;
+            if (len < 0) len += n;
+            len += 1;
+            // reverse positions i..j of the tour and i..j-1 of the edge lengths:
+            // pair q swaps tour[i+q] and tour[j-q], and elen[i+q] and
+            // elen[j-1-q] (for even lengths the middle pair of the lengths is
+            // one cell swapped with itself)
+            const int half = len / 2;
+            for (int q = t; q < half; q += nthr) {
                 int p = mv.i + q;
                 if (p >= n) p -= n;
                 int r = mv.j - q;
                 if (r < 0) r += n;
+                int r1 = r - 1;
+                if (r1 < 0) r1 += n;
                 const uint16_t tp = tour[p], tr = tour[r];
+                int32_t ep = 0, er = 0;
+                if (kLen) {
+                    ep = elen[p];
+                    er = elen[r1];
+                }
                 tour[p] = tr;
                 tour[r] = tp;
                 pos[tr] = (uint16_t)p;
                 pos[tp] = (uint16_t)r;
-            }
-            if (kLen) {  // the edges inside the path keep their lengths, in reverse order
-                for (int q = t; q < (len - 1) / 2; q += nthr) {
-                    int p = mv.i + q;
-                    if (p >= n) p -= n;
-                    int r = mv.j - 1 - q;
-                    if (r < 0) r += n;
-                    const int32_t ep = elen[p], er = elen[r];
+                if (kLen) {
                     elen[p] = er;
-                    elen[r] = ep;
+                    elen[r1] = ep;
                 }
             }
-        }
-        __syncthreads();
-        if (t == 0) {
-            int active = act - gstar;
-            if (moved) {
-                if (kLen) {  // the two new edges close the reversed path
-                    const int pl = mv.i == 0 ? n - 1 : mv.i - 1;
-                    const int x = tour[pl];
-                    const bool left_ac = x == mv.a || x == mv.c;
-                    elen[pl] = left_ac ? mv.dac : mv.da1c1;
-                    elen[mv.j] = left_ac ? mv.da1c1 : mv.dac;
-                }
-                const int ends[4] = {mv.a, mv.a1, mv.c, mv.c1};
-                for (int e = 0; e < 4; ++e) {
-                    const uint32_t bit = 1u << (ends[e] & 31);
-                    if (dlb[ends[e] >> 5] & bit) {
-                        dlb[ends[e] >> 5] &= ~bit;
-                        active += 1;
-                    }
-                }
-                s_cursor = mv.a;
-            } else {
-                const int last = s_list[count - 1];
-                s_cursor = last + 1 == n ? 0 : last + 1;
+            if (kLen && t == 0) {  // the two new edges close the reversed path
+                const int pl = mv.i == 0 ? n - 1 : mv.i - 1;
+                const bool left_ac = (mv.flags >> 4) & 1;
+                elen[pl] = left_ac ? mv.dac : mv.da1c1;
+                elen[mv.j] = left_ac ? mv.da1c1 : mv.dac;
             }
-            s_active = active;
+            a0 = mv.a;
+        } else {
+            a0 = last + 1 == n ? 0 : last + 1;
         }
+        act = newact;
     }
+    __syncthreads();
     // write back; the tour length from the final edges
     int64_t tl = 0;
     for (int i = t; i < n; i += nthr) {
