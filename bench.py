@@ -229,7 +229,7 @@ def main():
 
     tours_per_s = w["ants"] * args.steps / elapsed
     out = {
-        "metric": "tours constructed/sec at n=1002 (1 GPU)",
+        "metric": f"tours constructed/sec at n={n}" + (" with 2-opt on every tour" if w["ls_nn"] else "") + " (1 GPU)",
         "value": tours_per_s,
         "unit": "tours/s",
         "n_gpus": 1,
