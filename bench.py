@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--ants-per-block", type=int, default=0)
     ap.add_argument("--table-rows", type=int, default=-1)
     ap.add_argument("--lanes-per-ant", type=int, default=64, choices=(32, 64))
+    ap.add_argument("--waves-per-ant", type=int, default=0, choices=(0, 1, 2, 4, 8, 16),
+                    help="construction waves per ant (0: from the ant count)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--batched", action="store_true",
@@ -187,7 +189,7 @@ def main():
     n = w["n"]
     col = M.Colony(dist, w["ants"], cand_len=w["cand_len"], alpha=w["alpha"], beta=w["beta"],
                    rho=w["rho"], seed=args.seed, tabu=args.tabu, pher=w["pher"], ls_nn=w["ls_nn"])
-    col.set_launch(args.ants_per_block, args.table_rows, args.lanes_per_ant)
+    col.set_launch(args.ants_per_block, args.table_rows, args.lanes_per_ant, args.waves_per_ant)
     stream = col.stream
 
     def step(it):
@@ -245,7 +247,7 @@ def main():
                    "alpha": w["alpha"], "beta": w["beta"], "rho": w["rho"], "tabu": args.tabu,
                    "pheromone": w["pher"], "instance": f"{w['kind']} seed {w['seed']}",
                    "ants_per_block": args.ants_per_block or 4, "table_rows": args.table_rows,
-                   "lanes_per_ant": args.lanes_per_ant},
+                   "lanes_per_ant": args.lanes_per_ant, "waves_per_ant": args.waves_per_ant or "auto"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload) if args.tabu == "bitmask" else None,

@@ -148,8 +148,13 @@ mmas_status mmas_construct(mmas_ctx* ctx, uint32_t iteration);
  * -1 = as many as fit (default), 0 = none, k = at most k. `lanes_per_ant`:
  * 64 (one ant per wave64, default, also for 0) or 32 (two ants per wave64,
  * each on a half; applies when 1 <= cand_len <= 32, with an even number of
- * ants per workgroup, else 64 is used). EINVAL for other values. */
-mmas_status mmas_set_launch(mmas_ctx* ctx, int32_t ants_per_block, int32_t table_rows, int32_t lanes_per_ant);
+ * ants per workgroup, else 64 is used). `waves_per_ant`: 1, 2, 4, 8 or 16
+ * waves serve each ant (one workgroup per ant: the first wave takes the
+ * steps, all of them share every all-city fallback; ignored with 32 lanes
+ * per ant); 0 (default) = the largest power of two up to 16 such that
+ * ants x waves fit the GPU's SIMDs once. EINVAL for other values. */
+mmas_status mmas_set_launch(mmas_ctx* ctx, int32_t ants_per_block, int32_t table_rows, int32_t lanes_per_ant,
+                            int32_t waves_per_ant);
 
 /* 2-opt on every ant's tour with ls_nn-nearest-neighbour lists and don't-look
  * bits (Sec. 5.7), as a sequential first-improvement search (cities in index

@@ -33,6 +33,7 @@ constexpr size_t kScratchBytes = 16;                       // per-ant counter of
 
 struct BitmaskTabu {
     uint32_t* bits;
+    __device__ void attach(uint8_t* lds, int) { bits = reinterpret_cast<uint32_t*>(lds); }
     __device__ void init(uint8_t* lds, int n, int lane) {
         bits = reinterpret_cast<uint32_t*>(lds);
         const int words = (n + 31) >> 5;
@@ -51,6 +52,11 @@ struct CompactTabu {
     uint16_t* entries;
     int L;
     int n;
+    __device__ void attach(uint8_t* lds, int n_) {
+        entries = reinterpret_cast<uint16_t*>(lds);
+        n = n_;
+        L = n_;
+    }
     __device__ void init(uint8_t* lds, int n_, int lane) {
         entries = reinterpret_cast<uint16_t*>(lds);
         n = n_;
@@ -164,6 +170,76 @@ __device__ uint32_t fallback_list(const uint16_t* list, int L, const W& weight, 
     return wave_select<4>(bcode, bnode);
 }
 
+// ---- several waves per ant: the fallback shared by the workgroup ----------
+
+// What the leading wave (the one taking the steps) hands to the helper waves
+// of its workgroup for a fallback, and their per-wave results.
+struct WideLds {
+    int need[2];         // step k needs the fallback: need[k & 1] (the leading
+                         // wave writes step k+1's flag while a helper may still
+                         // read step k's)
+    uint32_t cur;        // current city
+    int L;               // compact tabu: unvisited count
+    uint32_t counter;    // bitmask tabu: list fill counter
+    unsigned long long res[16];  // per wave: (key code << 32) | ~city, 0 = none
+};
+
+// The unvisited cities of a bitmask tabu gathered by the whole workgroup
+// (thread t takes words t, t + threads, ...); `counter` is 0 on entry.
+__device__ void gather_unvisited_block(const BitmaskTabu& tabu, int n, uint16_t* list, uint32_t* counter) {
+    const int words = (n + 31) >> 5;
+    for (int wi = threadIdx.x; wi < words; wi += blockDim.x) {
+        uint32_t fr = ~tabu.bits[wi];
+        if (wi == words - 1 && (n & 31)) fr &= (1u << (n & 31)) - 1u;
+        if (fr) {
+            int p = (int)atomicAdd(counter, (uint32_t)__popc(fr));
+            while (fr) {
+                const int b = __ffs(fr) - 1;
+                fr &= fr - 1u;
+                list[p++] = (uint16_t)(wi * 32 + b);
+            }
+        }
+    }
+}
+
+// This wave's share of a workgroup-wide fallback (entries wave*64 + lane,
+// then every 64*waves): its best (key code, lowest city), packed so that the
+// larger value is the better one; 0 if the wave saw no city.
+template <class W>
+__device__ unsigned long long fallback_share(const uint16_t* list, int L, const W& weight, int cl, uint64_t seed,
+                                             uint32_t it, uint32_t ant, uint32_t step, int lane, int wv, int nw) {
+    uint32_t bcode = 0u, bnode = kNone;
+    const int stride = kWave * nw;
+    for (int base = wv * kWave; base < L; base += 4 * stride) {
+        uint32_t v[4];
+        float w[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + u * stride + lane;
+            v[u] = i < L ? (uint32_t)list[i] : kNone;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w[u] = v[u] != kNone ? weight(v[u]) : 1.0f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (v[u] == kNone) continue;
+            const uint32_t slot = (uint32_t)cl + v[u];
+            const Words4 blk = draw_block(seed, it, ant, step, slot);
+            const float key = log_u01(u01(pick_word(blk, slot & 3u))) / w[u];
+            keep_best(ord_key(key), v[u], bcode, bnode);
+        }
+    }
+    const uint32_t bc = wave_max_u32<4>(bcode);
+    if (bc == 0u) return 0ull;
+    const uint64_t tied = __ballot(bcode == bc);
+    uint32_t node;
+    if (__popcll(tied) == 1)
+        node = (uint32_t)__builtin_amdgcn_readlane((int)bnode, __ffsll((unsigned long long)tied) - 1);
+    else
+        node = wave_min_u32<4>(bcode == bc ? bnode : kNone);
+    return ((unsigned long long)bc << 32) | (unsigned long long)(~node);
+}
+
 // LDS layout of one workgroup: the candidate table of cities 0..R-1 (ids,
 // then choice_info), then one region per ant (its draws, its tabu and, for
 // the bitmask, room to list the unvisited cities during a fallback).
@@ -188,16 +264,24 @@ __device__ void stage_table(const Views& vw, int cl, int R, uint16_t* tcand, flo
 // One ant's tour (one wave64): start city, n - 1 selection steps, tour and
 // length stores. `region` is the ant's LDS region; rows 0..R-1 of the
 // candidate table are in LDS at tcand / tchc.
-template <int kTabu, int kPher>
+// With kWide the whole workgroup serves one ant: wave 0 takes the steps and
+// the other waves join it for every fallback (wl: the workgroup's WideLds).
+template <int kTabu, int kPher, bool kWide = false>
 __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int ant, int lane, uint8_t* region,
-                              const uint16_t* tcand, const float* tchc, int R) {
+                              const uint16_t* tcand, const float* tchc, int R, WideLds* wl = nullptr) {
     const int n = s.n, cl = s.cl;
     const uint64_t seed = s.seed;
+    const int wv = kWide ? (int)(threadIdx.x >> 6) : 0;
+    const int nw = kWide ? (int)(blockDim.x >> 6) : 1;
+    const bool lead = wv == 0;
 
     // per-ant LDS: the draws of the next steps (256 floats), then the tabu
     float* lnbuf = reinterpret_cast<float*>(region);
     typename TabuOf<kTabu>::type tabu;
-    tabu.init(region + kDrawBytes + kScratchBytes, n, lane);
+    if (lead)
+        tabu.init(region + kDrawBytes + kScratchBytes, n, lane);
+    else
+        tabu.attach(region + kDrawBytes + kScratchBytes, n);
     uint16_t* ulist = reinterpret_cast<uint16_t*>(region + kDrawBytes + kScratchBytes + align16(4 * ((n + 31) / 32)));
 
     float tmin_a = 0.0f;
@@ -211,7 +295,7 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
     // start city: floor(x * n / 2^32) of draw (step 0, slot 0)
     const uint32_t x0 = draw_block(seed, it, (uint32_t)ant, 0u, 0u).w[0];
     const uint32_t start = (uint32_t)(((uint64_t)x0 * (uint64_t)n) >> 32);
-    tabu.mark(start, lane);
+    if (lead) tabu.mark(start, lane);
 
     // Candidate draws are generated ahead, S steps at a time: lane l computes
     // the Philox block of step k + l/G and slots 4(l%G)..4(l%G)+3 and stores
@@ -231,7 +315,7 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
 
     for (int k = 1; k < n; ++k) {
         uint32_t next = kNone;
-        if (cl > 0) {
+        if (lead && cl > 0) {
             // candidate phase: lane r holds rank r of cur's list
             // every lane loads a valid entry (lanes past the list repeat the
             // last one and get no key); the row comes from LDS or from global
@@ -267,7 +351,58 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
             const uint32_t code = live ? ord_key(key) : 0u;
             next = cl <= 32 ? wave_select<2>(code, node) : wave_select<4>(code, node);
         }
-        if (next == kNone) {
+        if constexpr (kWide) {
+            // the helpers learn whether this step needs them
+            if (lead && lane == 0) {
+                wl->need[k & 1] = next == kNone ? 1 : 0;
+                wl->cur = cur;
+                if constexpr (kTabu == MMAS_TABU_BITMASK) wl->counter = 0u;
+                else wl->L = tabu.L;
+            }
+            __syncthreads();
+            const bool need = wl->need[k & 1] != 0;
+            if (need) {
+                if (lead) {
+                    fb_steps += 1;
+                    fb_nodes += n - k;
+                }
+                const uint32_t fcur = wl->cur;
+                const uint16_t* list;
+                int L;
+                if constexpr (kTabu == MMAS_TABU_BITMASK) {
+                    gather_unvisited_block(tabu, n, ulist, &wl->counter);
+                    __syncthreads();
+                    L = (int)wl->counter;
+                    list = ulist;
+                } else {
+                    L = wl->L;
+                    list = tabu.entries;
+                }
+                unsigned long long mine;
+                if constexpr (kPher == MMAS_PHER_DENSE) {
+                    const DenseWeight wt{vw.choice + (size_t)fcur * n};
+                    mine = fallback_share(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw);
+                } else {
+                    const CandWeight wt{dist + (size_t)fcur * n, tmin_a, s.beta};
+                    mine = fallback_share(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw);
+                }
+                if (lane == 0) wl->res[wv] = mine;
+                __syncthreads();
+                unsigned long long best = lane < nw ? wl->res[lane] : 0ull;
+                for (int o = 32; o >= 1; o >>= 1) {
+                    const unsigned long long other = __shfl_xor(best, o);
+                    best = other > best ? other : best;
+                }
+                next = (best >> 32) ? ~(uint32_t)best : kNone;
+                // (cur, L, the counter and the list of this step are read before
+                // the last barrier; res is written again only after the next
+                // step's first barrier)
+            }
+            if (!lead) {
+                if (need && next >= (uint32_t)n) break;  // the leading wave breaks too
+                continue;
+            }
+        } else if (next == kNone) {
             fb_steps += 1;
             fb_nodes += n - k;
             const uint16_t* list;
@@ -310,6 +445,7 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
             prev_last = (uint32_t)__builtin_amdgcn_readlane((int)tbuf, slot);
         }
     }
+    if (!lead) return;
     if (lane == 0) len += dist[(size_t)cur * n + start];  // closing edge
     len = wave_sum_i64(len);
     if (lane == 0) {
@@ -527,6 +663,21 @@ __global__ __launch_bounds__(1024) void k_construct(Views vw, Shape s, uint32_t 
         construct_ant<kTabu, kPher>(vw, s, it, ant, lane, regions + (size_t)wave * lds.per_ant, tcand, tchc, R);
 }
 
+// One ant per workgroup of several waves (construct_ant with kWide): the
+// table part of LDS, then the ant's region.
+template <int kTabu, int kPher>
+__global__ __launch_bounds__(1024) void k_construct_wide(Views vw, Shape s, uint32_t it, Lds lds) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    __shared__ WideLds wl;
+    const int lane = threadIdx.x & 63;
+    const int R = lds.rows;
+    uint16_t* tcand = reinterpret_cast<uint16_t*>(smem);
+    float* tchc = reinterpret_cast<float*>(smem + align16(R * s.cl * 2));
+    if (R > 0) stage_table(vw, s.cl, R, tcand, tchc);
+    __syncthreads();
+    construct_ant<kTabu, kPher, true>(vw, s, it, (int)blockIdx.x, lane, smem + lds.table_bytes, tcand, tchc, R, &wl);
+}
+
 // Batched construction: a persistent grid pulls tiles (instance, first ant of
 // a group of ants_per_block ants) from a queue ordered by decreasing n. Each
 // tile stages as many candidate rows of its instance as fit in the table part
@@ -628,9 +779,57 @@ hipError_t launch_t(const Views& v, const Shape& s, uint32_t it, hipStream_t st)
     return hipGetLastError();
 }
 
+// Waves per ant for the construction: the launch option, or (0) as many as
+// the SIMDs left over by one wave per ant allow, a power of two up to 16.
+int construct_waves(const Shape& s) {
+    if (s.construct_waves > 0) return s.construct_waves;
+    static int simds = -1;
+    if (simds < 0) {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+            simds = 4 * cus;
+        else
+            simds = 0;
+    }
+    int w = 1;
+    while (w < 16 && 2 * w * s.ants <= simds) w *= 2;
+    return w;
+}
+
+template <int kTabu, int kPher>
+hipError_t launch_wide(const Views& v, const Shape& s, uint32_t it, int waves, hipStream_t st) {
+    const int per_ant = (int)construct_lds_per_ant(s);
+    const int budget = max_lds_per_block() - (int)sizeof(WideLds) - 64;
+    if (per_ant > budget) return hipErrorInvalidValue;
+    Lds lds{};
+    lds.per_ant = per_ant;
+    int rows = 0;
+    if (s.cl > 0) {
+        rows = (budget - per_ant - 32) / (s.cl * 6);
+        if (rows > s.n) rows = s.n;
+        if (s.table_rows >= 0 && rows > s.table_rows) rows = s.table_rows;
+        while (rows > 0 && align16(rows * s.cl * 2) + align16(rows * s.cl * 4) + per_ant > budget) --rows;
+        if (rows < 0) rows = 0;
+    }
+    lds.rows = rows;
+    lds.table_bytes = align16(rows * s.cl * 2) + align16(rows * s.cl * 4);
+    const size_t bytes = (size_t)lds.table_bytes + (size_t)per_ant;
+    auto kern = k_construct_wide<kTabu, kPher>;
+    if (bytes > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    kern<<<s.ants, 64 * waves, bytes, st>>>(v, s, it, lds);
+    return hipGetLastError();
+}
+
 template <int kTabu, int kPher>
 hipError_t launch_tp(const Views& v, const Shape& s, uint32_t it, hipStream_t st) {
-    return pair_ok(s) ? launch_t<kTabu, kPher, true>(v, s, it, st) : launch_t<kTabu, kPher, false>(v, s, it, st);
+    if (pair_ok(s)) return launch_t<kTabu, kPher, true>(v, s, it, st);
+    const int waves = construct_waves(s);
+    if (waves > 1) return launch_wide<kTabu, kPher>(v, s, it, waves, st);
+    return launch_t<kTabu, kPher, false>(v, s, it, st);
 }
 
 // the persistent batched kernel for a configuration

@@ -44,6 +44,7 @@ struct Shape {
     uint64_t seed;
     int ants_per_block;  // construction launch: ants per workgroup
     int lanes_per_ant;   // construction launch: 64 (one ant per wave) or 32 (two)
+    int construct_waves; // construction launch: waves per ant (0 = from the ant count)
     int table_rows;      // rows of the candidate table staged in LDS (-1: all that fit)
     int two_opt_waves;   // 2-opt launch: waves per ant (1..16)
 };

@@ -66,6 +66,7 @@ Shape shape_of(const mmas_params* p) {
     s.ants_per_block = 4;
     s.table_rows = -1;
     s.lanes_per_ant = 64;
+    s.construct_waves = 0;
     s.two_opt_waves = 4;
     return s;
 }
@@ -235,8 +236,12 @@ mmas_status mmas_construct(mmas_ctx* c, uint32_t iteration) {
     return MMAS_OK;
 }
 
-mmas_status mmas_set_launch(mmas_ctx* c, int32_t ants_per_block, int32_t table_rows, int32_t lanes_per_ant) {
+mmas_status mmas_set_launch(mmas_ctx* c, int32_t ants_per_block, int32_t table_rows, int32_t lanes_per_ant,
+                            int32_t waves_per_ant) {
     if (!c) return MMAS_EINVAL;
+    if (waves_per_ant != 0 && waves_per_ant != 1 && waves_per_ant != 2 && waves_per_ant != 4 && waves_per_ant != 8 &&
+        waves_per_ant != 16)
+        return MMAS_EINVAL;
     if (ants_per_block != 0 && ants_per_block != 1 && ants_per_block != 2 && ants_per_block != 4 &&
         ants_per_block != 8 && ants_per_block != 16)
         return MMAS_EINVAL;
@@ -245,6 +250,7 @@ mmas_status mmas_set_launch(mmas_ctx* c, int32_t ants_per_block, int32_t table_r
     c->s.ants_per_block = ants_per_block == 0 ? 4 : ants_per_block;
     c->s.table_rows = table_rows;
     c->s.lanes_per_ant = lanes_per_ant == 0 ? 64 : lanes_per_ant;
+    c->s.construct_waves = waves_per_ant;
     return MMAS_OK;
 }
 

@@ -103,7 +103,7 @@ def _load():
     for name in ("mmas_prepare_choice_info", "mmas_two_opt", "mmas_update_pheromone", "mmas_synchronize"):
         getattr(L, name).argtypes = [p]
         getattr(L, name).restype = C.c_int
-    L.mmas_set_launch.argtypes = [p, C.c_int32, C.c_int32, C.c_int32]
+    L.mmas_set_launch.argtypes = [p, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
     L.mmas_set_launch.restype = C.c_int
     L.mmas_set_two_opt_launch.argtypes = [p, C.c_int32]
     L.mmas_set_two_opt_launch.restype = C.c_int
@@ -263,8 +263,9 @@ class Colony:
     def construct(self, iteration: int):
         _check(lib.mmas_construct(self._ctx, iteration), "mmas_construct")
 
-    def set_launch(self, ants_per_block=0, table_rows=-1, lanes_per_ant=64):
-        _check(lib.mmas_set_launch(self._ctx, ants_per_block, table_rows, lanes_per_ant), "mmas_set_launch")
+    def set_launch(self, ants_per_block=0, table_rows=-1, lanes_per_ant=64, waves_per_ant=0):
+        _check(lib.mmas_set_launch(self._ctx, ants_per_block, table_rows, lanes_per_ant, waves_per_ant),
+               "mmas_set_launch")
 
     def two_opt(self):
         _check(lib.mmas_two_opt(self._ctx), "mmas_two_opt")

@@ -191,19 +191,25 @@ def test_error_paths(gpu):
 
 
 @pytest.mark.parametrize("launch,tabu,pher,cl,ants", [
-    ((1, 0, 64), "bitmask", "dense", 32, 101),
-    ((8, -1, 64), "compact", "dense", 32, 101),
-    ((16, 50, 64), "bitmask", "candidates", 20, 64),
-    ((2, -1, 32), "bitmask", "dense", 32, 101),
-    ((4, 0, 32), "compact", "dense", 32, 101),
-    ((8, 60, 32), "bitmask", "candidates", 16, 64),
-    ((16, -1, 32), "compact", "candidates", 7, 33),
-    ((4, -1, 32), "bitmask", "dense", 0, 20),  # no list: 32 lanes fall back to one ant per wave
+    ((1, 0, 64, 1), "bitmask", "dense", 32, 101),
+    ((8, -1, 64, 1), "compact", "dense", 32, 101),
+    ((16, 50, 64, 1), "bitmask", "candidates", 20, 64),
+    ((2, -1, 32, 0), "bitmask", "dense", 32, 101),
+    ((4, 0, 32, 0), "compact", "dense", 32, 101),
+    ((8, 60, 32, 0), "bitmask", "candidates", 16, 64),
+    ((16, -1, 32, 0), "compact", "candidates", 7, 33),
+    ((4, -1, 32, 1), "bitmask", "dense", 0, 20),  # no list: 32 lanes fall back to one ant per wave
+    ((0, -1, 64, 2), "bitmask", "dense", 32, 101),
+    ((0, 0, 64, 4), "compact", "dense", 32, 64),
+    ((0, 40, 64, 8), "bitmask", "candidates", 16, 33),
+    ((0, -1, 64, 16), "compact", "candidates", 5, 20),
+    ((0, -1, 64, 16), "bitmask", "dense", 0, 20),  # every step is a fallback
+    ((0, 0, 64, 0), "bitmask", "dense", 32, 101),  # waves from the ant count
 ])
 def test_launch_shapes_match_oracle(gpu, launch, tabu, pher, cl, ants):
-    """Ants per workgroup, LDS table rows and two ants per wave (32 lanes
-    each) never change tours, lengths, fallback counts or trails; odd ant
-    counts leave the last wave with one ant."""
+    """Ants per workgroup, LDS table rows, two ants per wave (32 lanes each)
+    and several waves per ant never change tours, lengths, fallback counts or
+    trails; odd ant counts leave the last wave with one ant."""
     _, d = I.make_instance("clustered", 230, seed=77, clusters=5, sigma=500.0)
     say(f"launch {launch} {tabu} {pher} cl={cl} ants={ants}")
     run_parity(d, 3, launch=launch, ants=ants, cand_len=cl, rho=0.05, seed=9, tabu=tabu, pher=pher)
