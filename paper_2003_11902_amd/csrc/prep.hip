@@ -83,59 +83,67 @@ __global__ __launch_bounds__(256) void k_nearest(const int32_t* __restrict__ d, 
     }
 }
 
-// Nearest-neighbour tour from city 0 (one workgroup; visited bits in LDS),
-// then its length.
-__global__ __launch_bounds__(1024) void k_nn_tour(const int32_t* __restrict__ d, int n,
-                                                  uint16_t* __restrict__ tour,
-                                                  mmas_device_state* __restrict__ st) {
+// Nearest-neighbour tour from city 0 (one wave; visited bits in LDS), then
+// its length. The candidate list is sorted by (d, index) and holds the cl
+// nearest cities, so when one of them is unvisited the first such is the
+// nearest unvisited city; only otherwise is the whole row scanned for the
+// smallest (d, index).
+__global__ __launch_bounds__(64) void k_nn_tour(const int32_t* __restrict__ d, const uint16_t* __restrict__ cand,
+                                                int cl, int n, uint16_t* __restrict__ tour,
+                                                mmas_device_state* __restrict__ st) {
     extern __shared__ uint32_t vis[];  // ceil(n/32) words
-    __shared__ uint64_t part[16];
-    __shared__ int64_t lpart[16];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x;
     const int words = (n + 31) >> 5;
-    for (int w = threadIdx.x; w < words; w += blockDim.x) vis[w] = 0u;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        vis[0] = 1u;
-        tour[0] = 0;
-    }
-    __syncthreads();
+    for (int w = lane; w < words; w += kWave) vis[w] = 0u;
+    if (lane == 0) vis[0] = 1u;
     int cur = 0;
-    for (int k = 1; k < n; ++k) {
-        const int32_t* row = d + (size_t)cur * n;
-        uint64_t best = ~0ull;
-        for (int j = threadIdx.x; j < n; j += blockDim.x) {
-            if ((vis[j >> 5] >> (j & 31)) & 1u) continue;
-            const uint64_t key = ((uint64_t)(uint32_t)row[j] << 32) | (uint32_t)j;
-            best = key < best ? key : best;
-        }
-        best = wave_min_u64(best);
-        if (lane == 0) part[wave] = best;
-        __syncthreads();
-        uint64_t m = part[0];
-        for (int w = 1; w < nw; ++w) m = part[w] < m ? part[w] : m;
-        const int nxt = (int)(m & 0xFFFFFFFFu);
-        if (threadIdx.x == 0) {
-            vis[nxt >> 5] |= 1u << (nxt & 31);
-            tour[k] = (uint16_t)nxt;
-        }
-        cur = nxt;
-        __syncthreads();
-    }
-    // length, closing edge included (tour was written by thread 0 only)
+    uint32_t tbuf = 0;       // lane (k & 63) holds the city of step k
+    uint32_t prev_last = 0;  // last city of the previous 64-step chunk
     int64_t len = 0;
-    for (int k = threadIdx.x; k < n; k += blockDim.x) {
-        const int a = tour[k], b = tour[(k + 1) % n];
-        len += d[(size_t)a * n + b];
+    for (int k = 1; k < n; ++k) {
+        int nxt = -1;
+        if (cl > 0) {
+            const uint32_t c = cand[(size_t)cur * cl + (lane < cl ? lane : cl - 1)];
+            const bool free = (lane < cl) & !((vis[c >> 5] >> (c & 31)) & 1u);
+            const uint64_t m = __ballot(free);
+            if (m) nxt = __builtin_amdgcn_readlane((int)c, __ffsll((unsigned long long)m) - 1);
+        }
+        if (nxt < 0) {
+            const int32_t* row = d + (size_t)cur * n;
+            uint64_t best = ~0ull;
+            for (int j = lane; j < n; j += kWave) {
+                const uint64_t key = ((uint64_t)(uint32_t)row[j] << 32) | (uint32_t)j;
+                const bool seen = (vis[j >> 5] >> (j & 31)) & 1u;
+                best = (!seen && key < best) ? key : best;
+            }
+            const uint64_t m = wave_min_u64(best);
+            if (m == ~0ull) {  // no unvisited city: unreachable for k < n
+                if (lane == 0) atomicOr(&st->flags, 8u);
+                return;
+            }
+            nxt = (int)(m & 0xFFFFFFFFu);
+        }
+        if (lane == 0) vis[nxt >> 5] |= 1u << (nxt & 31);
+        const int slot = k & 63;
+        if (lane == slot) tbuf = (uint32_t)nxt;
+        cur = nxt;
+        if (slot == 63 || k == n - 1) {
+            const int k0 = k - slot;
+            const uint32_t prev = __shfl_up(tbuf, 1);
+            if (lane <= slot) {
+                tour[k0 + lane] = (uint16_t)tbuf;
+                const uint32_t from = lane == 0 ? prev_last : prev;
+                if (k0 + lane > 0) len += d[(size_t)from * n + tbuf];
+            }
+            prev_last = (uint32_t)__builtin_amdgcn_readlane((int)tbuf, slot);
+        }
     }
-    for (int o = 32; o >= 1; o >>= 1) len += __shfl_xor(len, o);
-    if (lane == 0) lpart[wave] = len;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t t = 0;
-        for (int w = 0; w < nw; ++w) t += lpart[w];
-        st->nn_len = t;
+    if (lane == 0) {
+        tour[0] = 0;
+        len += d[(size_t)cur * n];  // closing edge back to city 0
     }
+    len = wave_sum_i64(len);
+    if (lane == 0) st->nn_len = len;
 }
 
 __global__ void k_init_state(mmas_device_state* st, float rho, int n, double pdec) {
@@ -194,7 +202,7 @@ hipError_t launch_nearest(const int32_t* dist, int n, int k, uint16_t* out, hipS
 
 hipError_t launch_nn_tour(const Views& v, const Shape& s, hipStream_t st) {
     const size_t lds = sizeof(uint32_t) * (size_t)((s.n + 31) / 32);
-    k_nn_tour<<<1, 1024, lds, st>>>(v.dist, s.n, v.nn_tour, v.state);
+    k_nn_tour<<<1, kWave, lds, st>>>(v.dist, v.cand, s.cl, s.n, v.nn_tour, v.state);
     return hipGetLastError();
 }
 
