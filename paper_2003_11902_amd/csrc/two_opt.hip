@@ -52,6 +52,45 @@ __device__ __forceinline__ int wave_incl_scan(int x, int lane) {
 
 __device__ __forceinline__ uint32_t dlb_bit(const uint32_t* dlb, int x) { return (dlb[x >> 5] >> (x & 31)) & 1u; }
 
+// The next `count` active cities (don't-look bit clear) from city a0,
+// cyclically, into `list`; one wave. Entries in order: the word of a0 from
+// bit a0&31, the following words, the word of a0 below bit a0&31; 64 words a
+// pass, until `count` cities are listed.
+__device__ void list_active(const uint32_t* dlb, int words, uint32_t lastmask, int a0, int count, uint16_t* list,
+                            int lane) {
+    const int w0 = a0 >> 5, b0 = a0 & 31;
+    int found = 0;
+    for (int base = 0; base <= words && found < count; base += kWave) {
+        const int e = base + lane;
+        uint32_t bits = 0u;
+        int w = 0;
+        if (e <= words) {
+            uint32_t m;
+            if (e == 0) {
+                w = w0;
+                m = 0xFFFFFFFFu << b0;
+            } else if (e < words) {
+                w = w0 + e;
+                if (w >= words) w -= words;
+                m = 0xFFFFFFFFu;
+            } else {
+                w = w0;
+                m = b0 ? ((1u << b0) - 1u) : 0u;
+            }
+            if (w == words - 1) m &= lastmask;
+            bits = ~dlb[w] & m;
+        }
+        const int cnt = __popc(bits);
+        const int incl = wave_incl_scan(cnt, lane);
+        int idx = found + incl - cnt;
+        while (bits && idx < count) {
+            list[idx++] = (uint16_t)(w * 32 + __ffs(bits) - 1);
+            bits &= bits - 1u;
+        }
+        found += __builtin_amdgcn_readlane(incl, 63);
+    }
+}
+
 // The 2-opt of one ant per workgroup. kLen: the tour's edge lengths are kept
 // in LDS by position (len[p] = d(tour[p], tour[p+1])), so a move evaluation
 // reads one distance from HBM instead of three.
@@ -107,55 +146,16 @@ __global__ __launch_bounds__(1024) void k_two_opt(Views vw, Shape s, const int32
     // against a search that would not end
     const long long max_rounds = 256ll * n + 4096;
     long long rounds = 0;
+    if (wave == 0) list_active(dlb, words, lastmask, 0, min(C, n), s_lists[1], lane);
     while (act > 0) {
         if (++rounds > max_rounds) {
             if (t == 0) atomicOr(&vw.state->flags, 16u);
             return;
         }
         const int count = min(C, act);
-        // Only wave 0 writes the bits (below), so it may list the next cities
-        // at once; the other waves' last reversal is ordered before this
-        // round's evaluation by the barrier after the list.
-        uint16_t* s_list = s_lists[rounds & 1];
+        uint16_t* s_list = s_lists[rounds & 1];  // listed by wave 0 at the end of the last round
 
-        // ---- the next `count` active cities from a0, cyclically ----
-        // (wave 0 alone) entries in order: the word of a0 from bit a0&31, the
-        // following words, the word of a0 below bit a0&31; 64 words a pass,
-        // until `count` cities are listed
-        if (wave == 0) {
-            const int w0 = a0 >> 5, b0 = a0 & 31;
-            int found = 0;
-            for (int base = 0; base <= words && found < count; base += kWave) {
-                const int e = base + lane;
-                uint32_t bits = 0u;
-                int w = 0;
-                if (e <= words) {
-                    uint32_t m;
-                    if (e == 0) {
-                        w = w0;
-                        m = 0xFFFFFFFFu << b0;
-                    } else if (e < words) {
-                        w = w0 + e;
-                        if (w >= words) w -= words;
-                        m = 0xFFFFFFFFu;
-                    } else {
-                        w = w0;
-                        m = b0 ? ((1u << b0) - 1u) : 0u;
-                    }
-                    if (w == words - 1) m &= lastmask;
-                    bits = ~dlb[w] & m;
-                }
-                const int cnt = __popc(bits);
-                const int incl = wave_incl_scan(cnt, lane);
-                int idx = found + incl - cnt;
-                while (bits && idx < count) {
-                    s_list[idx++] = (uint16_t)(w * 32 + __ffs(bits) - 1);
-                    bits &= bits - 1u;
-                }
-                found += __builtin_amdgcn_readlane(incl, 63);
-            }
-        }
-        __syncthreads();  // s_list complete
+        __syncthreads();  // the list, the tour, positions, lengths and bits of this round
 
         // ---- evaluate every candidate move of the listed cities ----
         const int g = t / gs, rl = t % gs;
@@ -232,21 +232,13 @@ __global__ __launch_bounds__(1024) void k_two_opt(Views vw, Shape s, const int32
         if (moved) mv = s_cand[best];
         const int gstar = moved ? (mv.key >> 6) : count;  // the listed cities before it have no move
         const int last = s_list[count - 1];
-        // the listed cities before the move's city get their bits set, except
-        // the move's end points, whose bits end clear (wave 0 only)
-        if (wave == 0)
-            for (int q = lane; q < gstar; q += kWave) {
-                const int x = s_list[q];
-                if (!moved || (x != mv.a1 && x != mv.c && x != mv.c1))
-                    atomicOr(&dlb[x >> 5], 1u << (x & 31));
-            }
         int newact = act - gstar;
+        const int ends[4] = {mv.a, mv.a1, mv.c, mv.c1};
         if (moved) {
             // an end point's bit is set after the listing if it was set before
             // the round or if it lies in the listed part before the move's city
             int span = mv.a - a0;
             if (span < 0) span += n;
-            const int ends[4] = {mv.a, mv.a1, mv.c, mv.c1};
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 int de = ends[e] - a0;
@@ -254,17 +246,34 @@ __global__ __launch_bounds__(1024) void k_two_opt(Views vw, Shape s, const int32
                 const bool was = ((mv.flags >> e) & 1) || (e > 0 && de < span);
                 newact += was ? 1 : 0;
             }
-            if (t < 4 && ((mv.flags >> t) & 1)) atomicAnd(&dlb[ends[t] >> 5], ~(1u << (ends[t] & 31)));  // wave 0
-            // reverse positions i..j of the tour and i..j-1 of the edge lengths
-            int len = mv.j - mv.i;
-            if (len < 0) len += n;
-            len += 1;
+        }
+        const int a0_next = moved ? mv.a : (last + 1 == n ? 0 : last + 1);
+        // Wave 0 owns the don't-look bits: the listed cities before the move's
+        // city get theirs set (except the move's end points, whose bits end
+        // clear), the end points' are cleared, and the next round's cities
+        // are listed while the other waves reverse the path.
+        if (wave == 0) {
+            for (int q = lane; q < gstar; q += kWave) {
+                const int x = s_list[q];
+                if (!moved || (x != mv.a1 && x != mv.c && x != mv.c1))
+                    atomicOr(&dlb[x >> 5], 1u << (x & 31));
+            }
+            if (moved && lane < 4 && ((mv.flags >> lane) & 1))
+                atomicAnd(&dlb[ends[lane] >> 5], ~(1u << (ends[lane] & 31)));
+            if (newact > 0)
+                list_active(dlb, words, lastmask, a0_next, min(C, newact), s_lists[(rounds + 1) & 1], lane);
+        }
+        if (moved && (wave > 0 || nwaves == 1)) {
             // reverse positions i..j of the tour and i..j-1 of the edge lengths:
             // pair q swaps tour[i+q] and tour[j-q], and elen[i+q] and
             // elen[j-1-q] (for even lengths the middle pair of the lengths is
             // one cell swapped with itself)
+            const int rt = nwaves == 1 ? t : t - kWave, rthr = nwaves == 1 ? nthr : nthr - kWave;
+            int len = mv.j - mv.i;
+            if (len < 0) len += n;
+            len += 1;
             const int half = len / 2;
-            for (int q = t; q < half; q += nthr) {
+            for (int q = rt; q < half; q += rthr) {
                 int p = mv.i + q;
                 if (p >= n) p -= n;
                 int r = mv.j - q;
@@ -286,16 +295,14 @@ __global__ __launch_bounds__(1024) void k_two_opt(Views vw, Shape s, const int32
                     elen[r1] = ep;
                 }
             }
-            if (kLen && t == 0) {  // the two new edges close the reversed path
+            if (kLen && rt == 0) {  // the two new edges close the reversed path
                 const int pl = mv.i == 0 ? n - 1 : mv.i - 1;
                 const bool left_ac = (mv.flags >> 4) & 1;
                 elen[pl] = left_ac ? mv.dac : mv.da1c1;
                 elen[mv.j] = left_ac ? mv.da1c1 : mv.dac;
             }
-            a0 = mv.a;
-        } else {
-            a0 = last + 1 == n ? 0 : last + 1;
         }
+        a0 = a0_next;
         act = newact;
     }
     __syncthreads();
