@@ -12,6 +12,8 @@
 // compact tabu of Sec. 4.1 (one 16-bit entry per city plus the length L).
 // Tours are gathered in a register (lane k % 64 holds step k) and stored 64
 // cities at a time; tour lengths accumulate at those flushes.
+#include <atomic>
+
 #include "device.hpp"
 #include "internal.hpp"
 
@@ -726,18 +728,25 @@ __global__ __launch_bounds__(1024) void k_batch_construct(const BatchItem* __res
 
 }  // namespace
 
-int max_lds_per_block() {
-    static int cached = -1;
-    if (cached < 0) {
-        int dev = 0, v = 65536;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
-            cached = v;
-        else
-            cached = 65536;
-    }
-    return cached;
+// Per-device attributes, read once per device (up to 64 devices).
+namespace {
+constexpr int kMaxDevices = 64;
+std::atomic<int> g_lds[kMaxDevices];
+std::atomic<int> g_simds[kMaxDevices];
+
+int device_attr(std::atomic<int>* cache, hipDeviceAttribute_t attr, int scale, int fallback) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return fallback;
+    int v = cache[dev].load(std::memory_order_relaxed);
+    if (v > 0) return v;
+    int a = 0;
+    v = hipDeviceGetAttribute(&a, attr, dev) == hipSuccess && a > 0 ? a * scale : fallback;
+    cache[dev].store(v, std::memory_order_relaxed);
+    return v;
 }
+}  // namespace
+
+int max_lds_per_block() { return device_attr(g_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, 1, 65536); }
 
 namespace {
 
@@ -783,15 +792,8 @@ hipError_t launch_t(const Views& v, const Shape& s, uint32_t it, hipStream_t st)
 // the SIMDs left over by one wave per ant allow, a power of two up to 16.
 int construct_waves(const Shape& s) {
     if (s.construct_waves > 0) return s.construct_waves;
-    static int simds = -1;
-    if (simds < 0) {
-        int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
-            simds = 4 * cus;
-        else
-            simds = 0;
-    }
+    // four SIMDs per compute unit
+    const int simds = device_attr(g_simds, hipDeviceAttributeMultiprocessorCount, 4, 0);
     int w = 1;
     while (w < 16 && 2 * w * s.ants <= simds) w *= 2;
     return w;
