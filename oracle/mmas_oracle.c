@@ -589,9 +589,21 @@ void orc_get_cand(const orc_colony* c, uint16_t* out) {
 }
 void orc_get_heuristic(const orc_colony* c, float* out) {
     int n = c->n;
+    if (c->pher_mode == ORC_PHER_DENSE && c->heur) {
+        memcpy(out, c->heur, sizeof(float) * (size_t)n * n);
+        return;
+    }
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j)
             out[(size_t)i * n + j] = (i == j) ? 0.0f : heur_of(c->dist[(size_t)i * n + j], c->beta);
+}
+/* Replaces the dense heuristic matrix (eta^beta, n*n) used from the next
+ * choice_info on, e.g. by a learned heuristic; -1 in candidate-only mode,
+ * which keeps no matrix. */
+int orc_set_heuristic(orc_colony* c, const float* heur) {
+    if (c->pher_mode != ORC_PHER_DENSE || !c->heur) return -1;
+    memcpy(c->heur, heur, sizeof(float) * (size_t)c->n * c->n);
+    return 0;
 }
 void orc_get_fallback(const orc_colony* c, int64_t* steps, int64_t* nodes) {
     memcpy(steps, c->fb_steps, sizeof(int64_t) * (size_t)c->ants);

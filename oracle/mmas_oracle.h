@@ -107,6 +107,7 @@ void orc_get_choice(const orc_colony* c, float* out);
 void orc_get_chc(const orc_colony* c, float* out);
 void orc_get_cand(const orc_colony* c, uint16_t* out);
 void orc_get_heuristic(const orc_colony* c, float* out); /* dense eta^beta, n*n */
+int orc_set_heuristic(orc_colony* c, const float* heur); /* dense mode: replace eta^beta (n*n); -1 otherwise */
 void orc_get_fallback(const orc_colony* c, int64_t* steps, int64_t* nodes);
 /* limits[0] = tau_min, limits[1] = tau_max */
 void orc_get_limits(const orc_colony* c, float* limits);

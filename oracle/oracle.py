@@ -60,6 +60,8 @@ def lib():
                      "orc_get_limits", "orc_get_iteration_best"):
             getattr(L, name).argtypes = [p, p]
         L.orc_get_fallback.argtypes = [p, p, p]
+        L.orc_set_heuristic.argtypes = [p, p]
+        L.orc_set_heuristic.restype = C.c_int
         L.orc_get_best.argtypes = [p, p]
         L.orc_get_best.restype = C.c_int64
         L.orc_get_nn_tour.argtypes = [p, p]
@@ -273,6 +275,14 @@ class Colony:
         out = np.zeros(self.n * self.n, dtype=np.float32)
         lib().orc_get_heuristic(self._h, _ptr(out))
         return out.reshape(self.n, self.n)
+
+    def set_heuristic(self, heur):
+        """Dense mode: use `heur` (n x n eta^beta, e.g. install_eta's) from the
+        next choice_info on."""
+        h = np.ascontiguousarray(heur, dtype=np.float32)
+        assert h.shape == (self.n, self.n)
+        if lib().orc_set_heuristic(self._h, _ptr(h)) != 0:
+            raise ValueError("set_heuristic needs dense trails")
 
     def fallback(self):
         s = np.zeros(self.ants, dtype=np.int64)

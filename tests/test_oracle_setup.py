@@ -91,3 +91,24 @@ def test_invalid_arguments_rejected(orc):
             orc.Colony(d, **args)
     with pytest.raises(ValueError):
         orc.Colony(d[:2, :2], ants=1)
+
+
+def test_set_heuristic_scale_invariance(orc):
+    """Replacing the heuristic by itself, or by itself times 2 (an exact
+    scaling of every weight and key), leaves the tours unchanged; a
+    candidate-only colony has no matrix to replace."""
+    _, d = I.make_instance("uniform", 60, seed=21)
+    ref = orc.Colony(d, 12, cand_len=8, rho=0.1, seed=5)
+    same = orc.Colony(d, 12, cand_len=8, rho=0.1, seed=5)
+    twice = orc.Colony(d, 12, cand_len=8, rho=0.1, seed=5)
+    same.set_heuristic(same.heuristic())
+    twice.set_heuristic(twice.heuristic() * np.float32(2))
+    assert np.array_equal(twice.heuristic(), ref.heuristic() * np.float32(2))
+    for it in range(3):
+        for c in (ref, same, twice):
+            c.iterate(it)
+        assert np.array_equal(ref.tours(), same.tours())
+        assert np.array_equal(ref.tours(), twice.tours())
+    cand = orc.Colony(d, 4, cand_len=8, pher_mode=orc.PHER_CANDIDATES)
+    with pytest.raises(ValueError):
+        cand.set_heuristic(np.ones((60, 60), np.float32))
