@@ -78,9 +78,22 @@ def cpu_baseline(dist, w, seed, budget_s):
         el = time.perf_counter() - t0
         if el >= budget_s or it >= 200:
             break
+    # and one thread, as the paper's CPU runs: a few iterations of a fresh colony
+    o1 = O.Colony(dist, w["ants"], cand_len=w["cand_len"], alpha=w["alpha"], beta=w["beta"],
+                  rho=w["rho"], seed=seed)
+    t1 = time.perf_counter()
+    it1 = 0
+    while True:
+        o1.iterate(it1, 1)
+        it1 += 1
+        el1 = time.perf_counter() - t1
+        if el1 >= budget_s / 3 or it1 >= 50:
+            break
     return {"value": w["ants"] * it / el, "unit": "tours/s", "cores": threads, "kind": "oracle",
             "sample": f"{it} full iterations (choice, construction of {w['ants']} tours, update) of the same "
-                      f"workload, OpenMP over ants, {el:.1f} s"}
+                      f"workload, OpenMP over ants, {el:.1f} s",
+            "value_1_core": w["ants"] * it1 / el1,
+            "sample_1_core": f"{it1} iterations of a fresh colony on one thread, {el1:.1f} s"}
 
 
 def run_batched(args):
@@ -92,10 +105,20 @@ def run_batched(args):
     from paper_2003_11902_amd import mmas as M
 
     t0 = time.perf_counter()
-    insts = I.batch_instances(args.batch_count)
-    dists = [d for _, d in insts]
-    params = [M.make_params(d.shape[0], d.shape[0], cand_len=32, rho=0.02, seed=1 + k, tabu=args.tabu)
-              for k, d in enumerate(dists)]
+    if args.batch_of:
+        # K colonies of one named workload, seeds 1..K (the same instance)
+        _, d0, w = I.workload_instance(args.batch_of)
+        dists = [d0] * args.batch_count
+        params = [M.make_params(w["n"], w["ants"], cand_len=w["cand_len"], alpha=w["alpha"], beta=w["beta"],
+                                rho=w["rho"], seed=1 + k, tabu=args.tabu, pher=w["pher"])
+                  for k in range(args.batch_count)]
+        workload = f"{args.batch_of} x {args.batch_count} colonies"
+    else:
+        insts = I.batch_instances(args.batch_count)
+        dists = [d for _, d in insts]
+        params = [M.make_params(d.shape[0], d.shape[0], cand_len=32, rho=0.02, seed=1 + k, tabu=args.tabu)
+                  for k, d in enumerate(dists)]
+        workload = f"batched{args.batch_count}"
     b = M.Batch(dists, params)
     setup_s = time.perf_counter() - t0
     apb, tb, lanes = b.tune()
@@ -118,16 +141,19 @@ def run_batched(args):
     for k, (d, p) in enumerate(zip(dists, params)):
         n = d.shape[0]
         fb = b.instance(k).fallback()[1].sum()
-        nbytes += algorithmic_bytes(n, min(32, n - 1), int(p.ants), float(fb))
+        nbytes += algorithmic_bytes(n, min(int(p.cand_len), n - 1), int(p.ants), float(fb))
     ms = elapsed / args.steps * 1e3
     achieved = nbytes / (ms * 1e-3) / 1e9
     out = {
-        "metric": "tours constructed/sec, batched instances (1 GPU)",
+        "metric": ("tours constructed/sec, batched instances (1 GPU)" if not args.batch_of
+                   else f"tours constructed/sec at n={dists[0].shape[0]}, {args.batch_count} colonies batched (1 GPU)"),
         "value": total_ants * args.steps / elapsed, "unit": "tours/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"batched{args.batch_count}", "instances": args.batch_count,
-                   "n_range": [100, 2000], "ants": "n per instance", "cand_len": 32, "rho": 0.02,
+        "config": {"workload": workload, "instances": args.batch_count,
+                   "n_range": [int(min(d.shape[0] for d in dists)), int(max(d.shape[0] for d in dists))],
+                   "ants": "n per instance" if not args.batch_of else int(params[0].ants),
+                   "cand_len": int(params[0].cand_len), "rho": float(params[0].rho),
                    "tabu": args.tabu, "graph": not args.no_graph, "ants_per_block": apb, "table_bytes": tb, "lanes_per_ant": lanes,
                    "total_ants": total_ants},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -157,6 +183,9 @@ def main():
                     help="time the batched workload (256 instances, n in [100, 2000], ants = n) "
                          "instead of the single colony")
     ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-of", default=None,
+                    help="with --batched: that many colonies of this named workload (seeds 1..K) instead of "
+                         "the mixed 256-instance batch")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (3 times) and exit; "
@@ -252,6 +281,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload) if args.tabu == "bitmask" else None,
                      "kernel": "k_construct", "kernel_ms": cons_ms,
+                     "construct_only_tours_per_s": w["ants"] / (cons_ms * 1e-3),
                      "bytes_per_launch": nbytes},
     }
     if not args.no_cpu:
