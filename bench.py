@@ -175,6 +175,8 @@ def main():
     ap.add_argument("--ants-per-block", type=int, default=0)
     ap.add_argument("--table-rows", type=int, default=-1)
     ap.add_argument("--lanes-per-ant", type=int, default=64, choices=(32, 64))
+    ap.add_argument("--cand-len", type=int, default=None,
+                    help="override the workload's candidate-list length (0: no list, every step is a fallback)")
     ap.add_argument("--waves-per-ant", type=int, default=0, choices=(0, 1, 2, 4, 8, 16),
                     help="construction waves per ant (0: from the ant count)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
@@ -215,6 +217,8 @@ def main():
     xy, dist, w = I.workload_instance(args.workload)
     if args.ants:
         w["ants"] = args.ants
+    if args.cand_len is not None:
+        w["cand_len"] = args.cand_len
     n = w["n"]
     col = M.Colony(dist, w["ants"], cand_len=w["cand_len"], alpha=w["alpha"], beta=w["beta"],
                    rho=w["rho"], seed=args.seed, tabu=args.tabu, pher=w["pher"], ls_nn=w["ls_nn"])
@@ -279,7 +283,8 @@ def main():
                    "lanes_per_ant": args.lanes_per_ant, "waves_per_ant": args.waves_per_ant or "auto"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload) if args.tabu == "bitmask" else None,
+                     "traffic": (measured_traffic(args.workload)
+                                 if args.tabu == "bitmask" and args.cand_len is None and not args.ants else None),
                      "kernel": "k_construct", "kernel_ms": cons_ms,
                      "construct_only_tours_per_s": w["ants"] / (cons_ms * 1e-3),
                      "bytes_per_launch": nbytes},

@@ -13,7 +13,9 @@ R global-best tours that contain it.
 Evaluation (time to gap): on one instance, plain MMAS runs B iterations; its
 final global best L_plain(B) and wall time T_plain set the bar. The learned
 run (features + inference + installation + MMAS) is timed until its global
-best first reaches L_plain(B). Reported: t*/T_plain per seed and the median.
+best first reaches L_plain(B). Reported: t*/T_plain per seed and the median,
+and the gaps of both runs' B-iteration lengths to L_ref, the best tour of a
+long MMAS run with 2-opt on the same instance.
 """
 from __future__ import annotations
 
@@ -194,6 +196,20 @@ def time_to_gap(params, dist, xy, seeds=range(1, 11), budget=500, ants=None, can
     return out
 
 
+def reference_length(dist, iterations=300, ants=64, cand_len=32, ls_nn=8, rho=0.02, seed=1000, log=print):
+    """L_ref: the best tour of a long plain MMAS run with 2-opt on every tour
+    (the yardstick the gaps are quoted against)."""
+    col = M.Colony(dist, ants, cand_len=cand_len, rho=rho, seed=seed, ls_nn=ls_nn)
+    t0 = time.perf_counter()
+    for it in range(iterations):
+        col.iterate(it)
+    _, L = col.best()
+    col.close()
+    log(f"[learned] reference: MMAS + 2-opt, {ants} ants, {iterations} iterations: {L} "
+        f"({time.perf_counter() - t0:.1f} s)")
+    return int(L)
+
+
 def main(argv=None):
     """Train on generated instances and report the time to gap as one JSON line."""
     import argparse
@@ -205,13 +221,15 @@ def main(argv=None):
     ap.add_argument("--count", type=int, default=2000)
     ap.add_argument("--n-lo", type=int, default=200)
     ap.add_argument("--n-hi", type=int, default=1000)
-    ap.add_argument("--label-seeds", type=int, default=4)
-    ap.add_argument("--label-iterations", type=int, default=100)
+    ap.add_argument("--label-seeds", type=int, default=8)
+    ap.add_argument("--label-iterations", type=int, default=300)
     ap.add_argument("--label-ants", type=int, default=64)
-    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--eval-n", type=int, default=3795)
     ap.add_argument("--eval-seeds", type=int, default=10)
-    ap.add_argument("--budget", type=int, default=1000)
+    ap.add_argument("--budget", type=int, default=500)
+    ap.add_argument("--ref-iterations", type=int, default=300,
+                    help="iterations of the MMAS + 2-opt run that gives the reference length")
     ap.add_argument("--eval-cand-len", type=int, default=32,
                     help="candidate-list length of both evaluated runs")
     args = ap.parse_args(argv)
@@ -225,12 +243,19 @@ def main(argv=None):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
     xy, dist = I.make_instance("uniform", args.eval_n, seed=5)
+    L_ref = reference_length(dist, iterations=args.ref_iterations)
     recs = time_to_gap(params, dist, xy, seeds=range(1, args.eval_seeds + 1), budget=args.budget,
                        cand_len=args.eval_cand_len)
+    for r in recs:
+        r["plain_gap"] = (r["plain_len"] - L_ref) / L_ref
+        r["learned_final_gap"] = (r["learned_final_len"] - L_ref) / L_ref if r["learned_final_len"] else None
     ratios = [r["ratio"] for r in recs if r["ratio"] is not None]
     out = {"metric": "time-to-gap learned vs plain", "eval_instance": f"uniform n={args.eval_n} seed 5",
            "budget_iterations": args.budget, "eval_cand_len": args.eval_cand_len, "reached": len(ratios), "seeds": len(recs),
            "median_ratio": float(np.median(ratios)) if ratios else None,
+           "reference_len": L_ref,
+           "median_plain_gap": float(np.median([r["plain_gap"] for r in recs])),
+           "median_learned_final_gap": float(np.median([r["learned_final_gap"] for r in recs])),
            "train_edges": int(X.shape[0]), "train_instances": args.count, "data_s": t_data,
            "train_s": t_train, "loss": hist, "runs": recs}
     print(json.dumps(out), flush=True)
