@@ -121,7 +121,7 @@ __device__ __forceinline__ void keep_best(uint32_t code, uint32_t node, uint32_t
 // 16-bit entry per city). Lanes claim their slots with an LDS atomic add, so
 // the order of the list varies; the fallback's result does not depend on it
 // (largest key, lowest city on ties). Returns their number.
-__device__ int gather_unvisited(const BitmaskTabu& tabu, int n, uint16_t* list, uint32_t* counter, int lane) {
+__device__ __forceinline__ int gather_unvisited(const BitmaskTabu& tabu, int n, uint16_t* list, uint32_t* counter, int lane) {
     const int words = (n + 31) >> 5;
     if (lane == 0) *counter = 0u;
     for (int w0 = 0; w0 < words; w0 += kWave) {
@@ -147,7 +147,7 @@ __device__ int gather_unvisited(const BitmaskTabu& tabu, int n, uint16_t* list, 
 // cl + v. Each lane takes four list entries per round and issues their weight
 // loads before the Philox and logarithm work, so the loads overlap it.
 template <class W>
-__device__ uint32_t fallback_list(const uint16_t* list, int L, const W& weight, int cl, uint64_t seed, uint32_t it,
+__device__ __forceinline__ uint32_t fallback_list(const uint16_t* list, int L, const W& weight, int cl, uint64_t seed, uint32_t it,
                                   uint32_t ant, uint32_t step, int lane) {
     uint32_t bcode = 0u, bnode = kNone;
     for (int base = 0; base < L; base += 4 * kWave) {
@@ -170,6 +170,15 @@ __device__ uint32_t fallback_list(const uint16_t* list, int L, const W& weight, 
         }
     }
     return wave_select<4>(bcode, bnode);
+}
+
+// The same as a call (not inlined): the single-colony kernel, whose one wave
+// per SIMD is bound by its per-step chain, keeps its step loop small this way.
+template <class W>
+__device__ __attribute__((noinline)) uint32_t fallback_list_call(const uint16_t* list, int L, const W& weight, int cl,
+                                                                 uint64_t seed, uint32_t it, uint32_t ant,
+                                                                 uint32_t step, int lane) {
+    return fallback_list(list, L, weight, cl, seed, it, ant, step, lane);
 }
 
 // ---- several waves per ant: the fallback shared by the workgroup ----------
@@ -208,7 +217,7 @@ __device__ void gather_unvisited_block(const BitmaskTabu& tabu, int n, uint16_t*
 // then every 64*waves): its best (key code, lowest city), packed so that the
 // larger value is the better one; 0 if the wave saw no city.
 template <class W>
-__device__ unsigned long long fallback_share(const uint16_t* list, int L, const W& weight, int cl, uint64_t seed,
+__device__ __forceinline__ unsigned long long fallback_share(const uint16_t* list, int L, const W& weight, int cl, uint64_t seed,
                                              uint32_t it, uint32_t ant, uint32_t step, int lane, int wv, int nw) {
     uint32_t bcode = 0u, bnode = kNone;
     const int stride = kWave * nw;
@@ -268,7 +277,7 @@ __device__ void stage_table(const Views& vw, int cl, int R, uint16_t* tcand, flo
 // candidate table are in LDS at tcand / tchc.
 // With kWide the whole workgroup serves one ant: wave 0 takes the steps and
 // the other waves join it for every fallback (wl: the workgroup's WideLds).
-template <int kTabu, int kPher, bool kWide = false>
+template <int kTabu, int kPher, bool kWide = false, bool kOutline = false>
 __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int ant, int lane, uint8_t* region,
                               const uint16_t* tcand, const float* tchc, int R, WideLds* wl = nullptr) {
     const int n = s.n, cl = s.cl;
@@ -363,7 +372,7 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
             }
             __syncthreads();
             const bool need = wl->need[k & 1] != 0;
-            if (need) {
+            if (__builtin_expect(need, 0)) {
                 if (lead) {
                     fb_steps += 1;
                     fb_nodes += n - k;
@@ -418,10 +427,12 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
             }
             if constexpr (kPher == MMAS_PHER_DENSE) {
                 const DenseWeight wt{vw.choice + (size_t)cur * n};
-                next = fallback_list(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+                next = kOutline ? fallback_list_call(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane)
+                                : fallback_list(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
             } else {
                 const CandWeight wt{dist + (size_t)cur * n, tmin_a, s.beta};
-                next = fallback_list(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+                next = kOutline ? fallback_list_call(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane)
+                                : fallback_list(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
             }
         }
         if (next >= (uint32_t)n) {
@@ -593,14 +604,14 @@ __device__ void construct_pair(const Views& vw, const Shape& s, uint32_t it, int
             if (tA) nextA = (uint32_t)__builtin_amdgcn_readlane((int)node, __ffs(tA) - 1);
             if (tB) nextB = (uint32_t)__builtin_amdgcn_readlane((int)node, 32 + __ffs(tB) - 1);
         }
-        if (nextA == kNone) {
+        if (__builtin_expect(nextA == kNone, 0)) {
             fbA_steps += 1;
             fbA_nodes += n - k;
             nextA = fallback_step<kTabu, kPher>(vw, s, it, antA, curA, k, tabA, regA, tmin_a, lane);
         }
         if (!hasB) {
             nextB = curB;  // an absent second ant stays at its (valid) start city
-        } else if (nextB == kNone) {
+        } else if (__builtin_expect(nextB == kNone, 0)) {
             fbB_steps += 1;
             fbB_nodes += n - k;
             nextB = fallback_step<kTabu, kPher>(vw, s, it, antB, curB, k, tabB, regB, tmin_a, lane);
@@ -662,7 +673,8 @@ __global__ __launch_bounds__(1024) void k_construct(Views vw, Shape s, uint32_t 
         construct_pair<kTabu, kPher>(vw, s, it, ant, ant + 1 < s.ants, lane, regions + (size_t)(2 * wave) * lds.per_ant,
                                      regions + (size_t)(2 * wave + 1) * lds.per_ant, tcand, tchc, R);
     else
-        construct_ant<kTabu, kPher>(vw, s, it, ant, lane, regions + (size_t)wave * lds.per_ant, tcand, tchc, R);
+        construct_ant<kTabu, kPher, false, true>(vw, s, it, ant, lane, regions + (size_t)wave * lds.per_ant, tcand,
+                                                 tchc, R);
 }
 
 // One ant per workgroup of several waves (construct_ant with kWide): the
