@@ -357,7 +357,10 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
             // branch-free: every lane of the list computes its key; visited
             // cities and lanes past the list contribute no key
             const float lnu = lnbuf[4 * j * G + (lane & (4 * G - 1))];
-            const float key = lnu / w;
+            float key = lnu / w;
+            // every lane divides (no exec mask): the division overlaps the
+            // visited-bit load instead of waiting for it
+            asm volatile("" : "+v"(key));
             const bool live = (lane < cl) & !tabu.visited(node);  // no short circuit: no exec mask
             const uint32_t code = live ? ord_key(key) : 0u;
             next = cl <= 32 ? wave_select<2>(code, node) : wave_select<4>(code, node);
@@ -585,7 +588,8 @@ __device__ void construct_pair(const Views& vw, const Shape& s, uint32_t it, int
             *reinterpret_cast<float4*>(lnbuf + 4 * hl) = lv;
         }
         const float lnu = lnbuf[4 * j * G + (hl & (4 * G - 1))];
-        const float key = lnu / w;
+        float key = lnu / w;
+        asm volatile("" : "+v"(key));  // every lane divides, overlapping the visited-bit load
         const Tabu mine = h ? tabB : tabA;  // this half's tabu
         const bool live = (hl < cl) & !mine.visited(node) & writer;
         const uint32_t code = live ? ord_key(key) : 0u;
