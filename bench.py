@@ -121,7 +121,7 @@ def run_batched(args):
         workload = f"batched{args.batch_count}"
     b = M.Batch(dists, params)
     setup_s = time.perf_counter() - t0
-    apb, tb, lanes = b.tune()
+    apb, tb, lanes, tuned_tabu = b.tune()
     if not args.no_graph:
         b.capture()
     for _ in range(args.warmup):
@@ -154,7 +154,7 @@ def run_batched(args):
                    "n_range": [int(min(d.shape[0] for d in dists)), int(max(d.shape[0] for d in dists))],
                    "ants": "n per instance" if not args.batch_of else int(params[0].ants),
                    "cand_len": int(params[0].cand_len), "rho": float(params[0].rho),
-                   "tabu": args.tabu, "graph": not args.no_graph, "ants_per_block": apb, "table_bytes": tb, "lanes_per_ant": lanes,
+                   "tabu": {0: "bitmask", 1: "compact"}[tuned_tabu], "graph": not args.no_graph, "ants_per_block": apb, "table_bytes": tb, "lanes_per_ant": lanes,
                    "total_ants": total_ants},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,

@@ -230,11 +230,18 @@ mmas_status mmas_batch_create(int32_t count, const int32_t* const* dists_host, c
 mmas_status mmas_batch_set_launch(mmas_batch* b, int32_t ants_per_block, int32_t table_bytes,
                                   int32_t lanes_per_ant);
 
+/* Tabu of the batch's constructions, MMAS_TABU_BITMASK or MMAS_TABU_COMPACT
+ * (tours never depend on it); keeps the launch shape, EUNSUPPORTED if that
+ * shape's LDS no longer fits. Drops a captured graph. */
+mmas_status mmas_batch_set_tabu(mmas_batch* b, int32_t tabu);
+
 /* Autotuner: times one construction launch for each ants_per_block in
- * {4, 8, 16}, the LDS table on and off, and 64 or 32 lanes per ant (32 where
- * allowed), keeps the fastest and reports it (any pointer may be NULL).
- * Trails are not touched. Synchronises; drops a captured graph. */
-mmas_status mmas_batch_tune(mmas_batch* b, int32_t* ants_per_block, int32_t* table_bytes, int32_t* lanes_per_ant);
+ * {4, 8, 16}, the LDS table on and off, 64 or 32 lanes per ant (32 where
+ * allowed) and the bitmask or the compact tabu, keeps the fastest and reports
+ * it (any pointer may be NULL). Trails are not touched. Synchronises; drops
+ * a captured graph. */
+mmas_status mmas_batch_tune(mmas_batch* b, int32_t* ants_per_block, int32_t* table_bytes, int32_t* lanes_per_ant,
+                            int32_t* tabu);
 
 /* Captures one step into a hipGraph; later steps replay it. */
 mmas_status mmas_batch_capture(mmas_batch* b);

@@ -33,7 +33,9 @@ struct mmas_batch {
     int total_rows;
     int max_tiles;
     int tabu, pher;
-    int per_ant;        // largest per-ant LDS region over the instances
+    int per_ant;        // largest per-ant LDS region over the instances (current tabu)
+    int per_ant_tabu[2];  // the same for the bitmask and the compact tabu
+    int table_request;  // table_bytes as last asked for (-1: all that fits)
     int ants_per_block;
     int lanes_per_ant;
     bool pair_ok;       // every instance has 1 <= cl <= 32
@@ -102,6 +104,14 @@ mmas_status launch_step(mmas_batch* b) {
     return e == hipSuccess ? MMAS_OK : mmas::hip_fail(e, "batched update launch");
 }
 
+// The tabu of every construction (the device reads no tabu field; the host
+// copies follow for the LDS sizes). The caller sets the launch shape again.
+void apply_tabu(mmas_batch* b, int tabu) {
+    b->tabu = tabu;
+    b->per_ant = b->per_ant_tabu[tabu];
+    for (auto& it : b->items) it.s.tabu = tabu;
+}
+
 void drop_graph(mmas_batch* b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -163,6 +173,7 @@ mmas_status mmas_batch_create(int32_t count, const int32_t* const* dists_host, c
     b->items.resize(count);
     std::vector<int> row_start(count + 1, 0);
     b->per_ant = 0;
+    b->per_ant_tabu[0] = b->per_ant_tabu[1] = 0;
     for (int i = 0; i < count; ++i) {
         const size_t w = mmas_workspace_bytes(&params[i]);
         r = mmas_create(dists_host[i], &params[i], b->ws + pos, w, hip_stream, &b->ctx[i]);
@@ -176,6 +187,11 @@ mmas_status mmas_batch_create(int32_t count, const int32_t* const* dists_host, c
         mmas::ctx_views(b->ctx[i], &b->items[i].v, &b->items[i].s);
         row_start[i + 1] = row_start[i] + b->items[i].s.n;
         b->per_ant = std::max(b->per_ant, (int)mmas::construct_lds_per_ant(b->items[i].s));
+        for (int t = 0; t < 2; ++t) {
+            mmas::Shape st = b->items[i].s;
+            st.tabu = t;
+            b->per_ant_tabu[t] = std::max(b->per_ant_tabu[t], (int)mmas::construct_lds_per_ant(st));
+        }
     }
     b->total_rows = row_start[count];
     b->order.resize(count);
@@ -198,6 +214,7 @@ mmas_status mmas_batch_create(int32_t count, const int32_t* const* dists_host, c
     for (int i = 0; i < count; ++i) b->pair_ok = b->pair_ok && b->items[i].s.cl >= 1 && b->items[i].s.cl <= 32;
     b->ants_per_block = 4;
     b->lanes_per_ant = 64;
+    b->table_request = -1;
     b->table_bytes = std::max(0, (mmas::max_lds_per_block() - kStaticLds - b->ants_per_block * b->per_ant) & ~15);
     r = rebuild_tiles(b);
     if (r != MMAS_OK) {
@@ -223,33 +240,46 @@ mmas_status mmas_batch_set_launch(mmas_batch* b, int32_t ants_per_block, int32_t
     drop_graph(b);
     b->ants_per_block = ants_per_block;
     b->lanes_per_ant = lanes;
+    b->table_request = table_bytes;
     b->table_bytes = table_bytes < 0 ? budget : std::min(budget, table_bytes & ~15);
     return rebuild_tiles(b);
 }
 
-mmas_status mmas_batch_tune(mmas_batch* b, int32_t* ants_per_block, int32_t* table_bytes, int32_t* lanes_per_ant) {
+mmas_status mmas_batch_set_tabu(mmas_batch* b, int32_t tabu) {
+    if (!b || (tabu != MMAS_TABU_BITMASK && tabu != MMAS_TABU_COMPACT)) return MMAS_EINVAL;
+    const int keep = b->tabu;
+    apply_tabu(b, tabu);
+    mmas_status r = mmas_batch_set_launch(b, b->ants_per_block, b->table_request, b->lanes_per_ant);
+    if (r != MMAS_OK) apply_tabu(b, keep);
+    return r;
+}
+
+mmas_status mmas_batch_tune(mmas_batch* b, int32_t* ants_per_block, int32_t* table_bytes, int32_t* lanes_per_ant,
+                            int32_t* tabu) {
     if (!b) return MMAS_EINVAL;
     struct Cand {
-        int apb, tb, lanes;
+        int apb, tb, lanes, tabu;
     };
     std::vector<Cand> cands;
-    for (int lanes : {64, 32}) {
-        if (lanes == 32 && !b->pair_ok) continue;
-        for (int apb : {4, 8, 16}) {
-            const int budget = mmas::max_lds_per_block() - kStaticLds - apb * b->per_ant;
-            if (budget < 0) continue;
-            cands.push_back({apb, -1, lanes});
-            cands.push_back({apb, 0, lanes});
+    for (int t : {MMAS_TABU_BITMASK, MMAS_TABU_COMPACT})
+        for (int lanes : {64, 32}) {
+            if (lanes == 32 && !b->pair_ok) continue;
+            for (int apb : {4, 8, 16}) {
+                const int budget = mmas::max_lds_per_block() - kStaticLds - apb * b->per_ant_tabu[t];
+                if (budget < 0) continue;
+                cands.push_back({apb, -1, lanes, t});
+                cands.push_back({apb, 0, lanes, t});
+            }
         }
-    }
     hipEvent_t e0, e1;
     hipError_t ee = hipEventCreate(&e0);
     if (ee == hipSuccess) ee = hipEventCreate(&e1);
     if (ee != hipSuccess) return mmas::hip_fail(ee, "tuner events");
     float best_ms = 1e30f;
-    Cand best = cands.empty() ? Cand{4, -1, 64} : cands[0];
+    Cand best = cands.empty() ? Cand{4, -1, 64, b->tabu} : cands[0];
     mmas_status r = MMAS_OK;
     for (const Cand& c : cands) {
+        apply_tabu(b, c.tabu);
         r = mmas_batch_set_launch(b, c.apb, c.tb, c.lanes);
         if (r != MMAS_OK) break;
         // construction only: it writes tours and lengths, never the trails
@@ -275,8 +305,10 @@ mmas_status mmas_batch_tune(mmas_batch* b, int32_t* ants_per_block, int32_t* tab
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (r != MMAS_OK) return r;
+    apply_tabu(b, best.tabu);
     r = mmas_batch_set_launch(b, best.apb, best.tb, best.lanes);
     if (r != MMAS_OK) return r;
+    if (tabu) *tabu = b->tabu;
     if (ants_per_block) *ants_per_block = b->ants_per_block;
     if (table_bytes) *table_bytes = b->table_bytes;
     if (lanes_per_ant) *lanes_per_ant = b->lanes_per_ant;

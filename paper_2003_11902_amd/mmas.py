@@ -55,7 +55,7 @@ EXPORTED = (
     "mmas_batch_capture", "mmas_batch_step", "mmas_batch_iteration", "mmas_batch_context",
     "mmas_batch_destroy", "mmas_mlp_param_count", "mmas_mlp_packed_count", "mmas_mlp_features",
     "mmas_mlp_pack", "mmas_mlp_forward", "mmas_mlp_grad", "mmas_mlp_adam", "mmas_mlp_labels",
-    "mmas_set_learned_heuristic", "mmas_last_error", "mmas_set_two_opt_launch",
+    "mmas_set_learned_heuristic", "mmas_last_error", "mmas_set_two_opt_launch", "mmas_batch_set_tabu",
 )
 
 
@@ -129,7 +129,10 @@ def _load():
     L.mmas_batch_create.restype = C.c_int
     L.mmas_batch_set_launch.argtypes = [p, C.c_int32, C.c_int32, C.c_int32]
     L.mmas_batch_set_launch.restype = C.c_int
-    L.mmas_batch_tune.argtypes = [p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.mmas_batch_tune.argtypes = [p, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_int32)]
+    L.mmas_batch_set_tabu.argtypes = [p, C.c_int32]
+    L.mmas_batch_set_tabu.restype = C.c_int
     L.mmas_batch_tune.restype = C.c_int
     for name in ("mmas_batch_capture", "mmas_batch_step"):
         getattr(L, name).argtypes = [p]
@@ -420,12 +423,17 @@ class Batch:
         _check(lib.mmas_batch_set_launch(self._h, ants_per_block, table_bytes, lanes_per_ant), "mmas_batch_set_launch")
 
     def tune(self):
-        """(ants_per_block, table_bytes, lanes_per_ant) chosen by the autotuner."""
+        """(ants_per_block, table_bytes, lanes_per_ant, tabu) chosen by the autotuner."""
         apb = C.c_int32()
         tb = C.c_int32()
         lanes = C.c_int32()
-        _check(lib.mmas_batch_tune(self._h, C.byref(apb), C.byref(tb), C.byref(lanes)), "mmas_batch_tune")
-        return int(apb.value), int(tb.value), int(lanes.value)
+        tabu = C.c_int32()
+        _check(lib.mmas_batch_tune(self._h, C.byref(apb), C.byref(tb), C.byref(lanes), C.byref(tabu)),
+               "mmas_batch_tune")
+        return int(apb.value), int(tb.value), int(lanes.value), int(tabu.value)
+
+    def set_tabu(self, tabu):
+        _check(lib.mmas_batch_set_tabu(self._h, TABU.get(tabu, tabu)), "mmas_batch_set_tabu")
 
     def capture(self):
         _check(lib.mmas_batch_capture(self._h), "mmas_batch_capture")

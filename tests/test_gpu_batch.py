@@ -81,9 +81,19 @@ def test_launch_shapes_and_tuner_do_not_change_results(gpu):
         for i in range(len(dists)):
             assert np.array_equal(b.instance(i).tours(), ref[i][1][0]), (apb, tb, lanes, i)
             assert np.array_equal(b.instance(i).lengths(), ref[i][1][2]), (apb, tb, lanes, i)
+    for tabu in ("compact", "bitmask"):
+        say(f"tabu {tabu}")
+        b = M.Batch(dists, params)
+        b.set_tabu(tabu)
+        b.set_launch(8, -1, 32)
+        b.step()
+        b.step()
+        b.synchronize()
+        for i in range(len(dists)):
+            assert np.array_equal(b.instance(i).tours(), ref[i][1][0]), (tabu, i)
     b = M.Batch(dists, params)
-    apb, tb, lanes = b.tune()
-    assert apb in (4, 8, 16) and lanes in (32, 64)
+    apb, tb, lanes, tabu = b.tune()
+    assert apb in (4, 8, 16) and lanes in (32, 64) and tabu in (0, 1)
     b.step()
     b.step()
     b.synchronize()
