@@ -92,3 +92,19 @@ def test_uniform3795_learned_full_iterations(gpu):
         o.iterate(it, 16)
         compare_iteration(g, o, it)
     assert g.state().flags == 0
+
+
+def test_large_n_first_iteration(gpu):
+    """n = 40000 (ids close to the 16-bit limit, per-ant LDS of 86 KB with the
+    bitmask tabu, helper waves on the all-city fallbacks): one iteration of
+    two ants with candidate-only trails against the oracle."""
+    from oracle import oracle as O
+    from paper_2003_11902_amd import mmas as M
+    _, d = I.make_instance("uniform", 40000, seed=77, side=1e6)
+    say("n = 40000: one iteration, 2 ants, cl 8")
+    g = M.Colony(d, 2, cand_len=8, rho=0.05, seed=9, pher="candidates")
+    o = O.Colony(d, 2, cand_len=8, rho=0.05, seed=9, pher_mode=O.PHER_CANDIDATES)
+    g.iterate(0)
+    o.iterate(0, 2)
+    compare_iteration(g, o, 0)
+    assert g.state().flags == 0
