@@ -357,13 +357,16 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
             // branch-free: every lane of the list computes its key; visited
             // cities and lanes past the list contribute no key
             const float lnu = lnbuf[4 * j * G + (lane & (4 * G - 1))];
+            // the visited-bit load is issued first, then every lane divides (no
+            // exec mask), so that the division overlaps the load
+            const bool seen = tabu.visited(node);
             float key = lnu / w;
-            // every lane divides (no exec mask): the division overlaps the
-            // visited-bit load instead of waiting for it
             asm volatile("" : "+v"(key));
-            const bool live = (lane < cl) & !tabu.visited(node);  // no short circuit: no exec mask
+            const bool live = (lane < cl) & !seen;  // no short circuit: no exec mask
             const uint32_t code = live ? ord_key(key) : 0u;
-            next = cl <= 32 ? wave_select<2>(code, node) : wave_select<4>(code, node);
+            // (all four rows even for cl <= 32: lanes past the list hold no key,
+            // and one code path is faster than two)
+            next = wave_select_step<4>(code, node);
         }
         if constexpr (kWide) {
             // the helpers learn whether this step needs them

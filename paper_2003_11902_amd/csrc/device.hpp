@@ -165,6 +165,18 @@ __device__ __forceinline__ uint32_t wave_select(uint32_t code, uint32_t node) {
     return wave_min_u32<kRows>(code == best ? node : 0xFFFFFFFFu);
 }
 
+// The same selection, laid out for the construction step: the first holder
+// of the best key is read before the (rare) test for a tie.
+template <int kRows = 4>
+__device__ __forceinline__ uint32_t wave_select_step(uint32_t code, uint32_t node) {
+    const uint32_t best = wave_max_u32<kRows>(code);
+    if (best == 0u) return 0xFFFFFFFFu;
+    const uint64_t tied = __ballot(code == best);
+    uint32_t sel = (uint32_t)__builtin_amdgcn_readlane((int)node, (int)__builtin_ctzll(tied));
+    if (__builtin_expect((tied & (tied - 1)) != 0, 0)) sel = wave_min_u32<kRows>(code == best ? node : 0xFFFFFFFFu);
+    return sel;
+}
+
 }  // namespace mmas
 
 namespace mmas {
