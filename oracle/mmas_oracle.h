@@ -45,9 +45,10 @@ uint32_t orc_draw_word(uint64_t seed, uint32_t it, uint32_t ant, uint32_t step, 
 float orc_u01(uint32_t x);
 
 /* Natural logarithm in FP32 for the random(0,1) draws of Sec. 4.2.2:
- * u = m * 2^e with m in (sqrt(2)/2, sqrt(2)], f = m - 1, s = f / (2 + f),
- * ln(1+f) = 2 atanh(s) from the odd atanh series through s^11, and
- * ln(u) = e*ln2 (split into a head that e multiplies exactly and a tail). */
+ * u = m * 2^e with m in (sqrt(2)/2, sqrt(2)], f = m - 1,
+ * ln(1+f) = f + f^2 Q(f) with a fitted degree-10 polynomial Q evaluated by
+ * fused multiply-adds, and ln(u) = e*ln2 + ln(1+f) (ln 2 split into a head
+ * that e multiplies exactly and a tail). */
 float orc_logf(float u);
 
 /* Array forms of the three above, for exhaustive tests. */
