@@ -117,39 +117,15 @@ __device__ __forceinline__ void keep_best(uint32_t code, uint32_t node, uint32_t
     }
 }
 
-// The unvisited cities of a bitmask tabu, gathered into `list` (LDS, one
-// 16-bit entry per city). Lanes claim their slots with an LDS atomic add, so
-// the order of the list varies; the fallback's result does not depend on it
-// (largest key, lowest city on ties). Returns their number.
-__device__ __forceinline__ int gather_unvisited(const BitmaskTabu& tabu, int n, uint16_t* list, uint32_t* counter, int lane) {
-    const int words = (n + 31) >> 5;
-    if (lane == 0) *counter = 0u;
-    for (int w0 = 0; w0 < words; w0 += kWave) {
-        const int wi = w0 + lane;
-        uint32_t fr = 0u;
-        if (wi < words) {
-            fr = ~tabu.bits[wi];
-            if (wi == words - 1 && (n & 31)) fr &= (1u << (n & 31)) - 1u;
-        }
-        if (fr) {
-            int p = (int)atomicAdd(counter, (uint32_t)__popc(fr));
-            while (fr) {
-                const int b = __ffs(fr) - 1;
-                fr &= fr - 1u;
-                list[p++] = (uint16_t)(wi * 32 + b);
-            }
-        }
-    }
-    return (int)*counter;
-}
-
-// All-node fallback over a list of the L unvisited cities: city v draws slot
-// cl + v. Each lane takes four list entries per round and issues their weight
-// loads before the Philox and logarithm work, so the loads overlap it.
+// Keys of an all-node fallback over `list` (the L unvisited cities, or a
+// part of them): city v draws slot cl + v. Each lane takes four list entries
+// per round and issues their weight loads before the Philox and logarithm
+// work, so the loads overlap it. Folds the best (code, city) of each lane
+// into bcode / bnode.
 template <class W>
-__device__ __forceinline__ uint32_t fallback_list(const uint16_t* list, int L, const W& weight, int cl, uint64_t seed, uint32_t it,
-                                  uint32_t ant, uint32_t step, int lane) {
-    uint32_t bcode = 0u, bnode = kNone;
+__device__ __forceinline__ void fallback_keys(const uint16_t* list, int L, const W& weight, int cl, uint64_t seed,
+                                              uint32_t it, uint32_t ant, uint32_t step, int lane, uint32_t& bcode,
+                                              uint32_t& bnode) {
     for (int base = 0; base < L; base += 4 * kWave) {
         uint32_t v[4];
         float w[4];
@@ -169,16 +145,79 @@ __device__ __forceinline__ uint32_t fallback_list(const uint16_t* list, int L, c
             keep_best(ord_key(key), v[u], bcode, bnode);
         }
     }
+}
+
+// All-node fallback over a list of the L unvisited cities (the compact tabu's
+// left part).
+template <class W>
+__device__ __forceinline__ uint32_t fallback_list(const uint16_t* list, int L, const W& weight, int cl, uint64_t seed,
+                                                  uint32_t it, uint32_t ant, uint32_t step, int lane) {
+    uint32_t bcode = 0u, bnode = kNone;
+    fallback_keys(list, L, weight, cl, seed, it, ant, step, lane, bcode, bnode);
     return wave_select<4>(bcode, bnode);
 }
 
-// The same as a call (not inlined): the single-colony kernel, whose one wave
+// Entries of the list a one-wave fallback over a bitmask tabu builds in LDS
+// (unless the launch allows more): the unvisited cities are listed and keyed
+// in passes of at most this many, so the ant's LDS does not grow with n.
+constexpr int kListCap = 512;
+__host__ __device__ inline int list_cap(const Shape& s) {
+    return s.list_cap > 0 ? s.list_cap : (s.n < kListCap ? s.n : kListCap);
+}
+
+// All-node fallback over a bitmask tabu. Each pass takes the next words (one
+// per lane, at most 64), keeps the longest run of them whose unvisited cities
+// fit in `cap` list entries (a wave prefix sum of their counts gives every
+// lane its first slot), lists those cities and keys them; the best key over
+// all passes wins (largest key, lowest city), as over one list of them all.
+template <class W>
+__device__ __forceinline__ uint32_t fallback_bitmask(const BitmaskTabu& tabu, int n, uint16_t* list, int cap,
+                                                     const W& weight, int cl, uint64_t seed, uint32_t it, uint32_t ant,
+                                                     uint32_t step, int lane) {
+    const int words = (n + 31) >> 5;
+    uint32_t bcode = 0u, bnode = kNone;
+    for (int w0 = 0; w0 < words;) {
+        const int wi = w0 + lane;
+        uint32_t fr = 0u;
+        if (wi < words) {
+            fr = ~tabu.bits[wi];
+            if (wi == words - 1 && (n & 31)) fr &= (1u << (n & 31)) - 1u;
+        }
+        const int cnt = __popc(fr);
+        const int incl = wave_incl_scan(cnt, lane);
+        // a prefix of the lanes (incl grows with the lane); lane 0 always
+        // fits, since one word holds at most 32 <= cap cities
+        const bool fits = (wi < words) & (incl <= cap);
+        const int nfit = __popcll(__ballot(fits));
+        const int L = __builtin_amdgcn_readlane(incl, nfit - 1);
+        if (fits) {
+            int p = incl - cnt;
+            while (fr) {
+                const int b = __ffs(fr) - 1;
+                fr &= fr - 1u;
+                list[p++] = (uint16_t)(wi * 32 + b);
+            }
+        }
+        fallback_keys(list, L, weight, cl, seed, it, ant, step, lane, bcode, bnode);
+        w0 += nfit;
+    }
+    return wave_select<4>(bcode, bnode);
+}
+
+// The same as calls (not inlined): the single-colony kernel, whose one wave
 // per SIMD is bound by its per-step chain, keeps its step loop small this way.
 template <class W>
 __device__ __attribute__((noinline)) uint32_t fallback_list_call(const uint16_t* list, int L, const W& weight, int cl,
                                                                  uint64_t seed, uint32_t it, uint32_t ant,
                                                                  uint32_t step, int lane) {
     return fallback_list(list, L, weight, cl, seed, it, ant, step, lane);
+}
+template <class W>
+__device__ __attribute__((noinline)) uint32_t fallback_bitmask_call(const BitmaskTabu& tabu, int n, uint16_t* list,
+                                                                    int cap, const W& weight, int cl, uint64_t seed,
+                                                                    uint32_t it, uint32_t ant, uint32_t step,
+                                                                    int lane) {
+    return fallback_bitmask(tabu, n, list, cap, weight, cl, seed, it, ant, step, lane);
 }
 
 // ---- several waves per ant: the fallback shared by the workgroup ----------
@@ -422,23 +461,23 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
         } else if (next == kNone) {
             fb_steps += 1;
             fb_nodes += n - k;
-            const uint16_t* list;
-            int L;
-            if constexpr (kTabu == MMAS_TABU_BITMASK) {
-                L = gather_unvisited(tabu, n, ulist, reinterpret_cast<uint32_t*>(region + kDrawBytes), lane);
-                list = ulist;
-            } else {
-                L = tabu.L;
-                list = tabu.entries;
-            }
+            const int cap = list_cap(s);
             if constexpr (kPher == MMAS_PHER_DENSE) {
                 const DenseWeight wt{vw.choice + (size_t)cur * n};
-                next = kOutline ? fallback_list_call(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane)
-                                : fallback_list(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+                if constexpr (kTabu == MMAS_TABU_BITMASK)
+                    next = kOutline ? fallback_bitmask_call(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane)
+                                    : fallback_bitmask(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+                else
+                    next = kOutline ? fallback_list_call(tabu.entries, tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane)
+                                    : fallback_list(tabu.entries, tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
             } else {
                 const CandWeight wt{dist + (size_t)cur * n, tmin_a, s.beta};
-                next = kOutline ? fallback_list_call(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane)
-                                : fallback_list(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+                if constexpr (kTabu == MMAS_TABU_BITMASK)
+                    next = kOutline ? fallback_bitmask_call(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane)
+                                    : fallback_bitmask(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+                else
+                    next = kOutline ? fallback_list_call(tabu.entries, tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane)
+                                    : fallback_list(tabu.entries, tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
             }
         }
         if (next >= (uint32_t)n) {
@@ -498,22 +537,22 @@ template <int kTabu, int kPher, class Tabu>
 __device__ uint32_t fallback_step(const Views& vw, const Shape& s, uint32_t it, uint32_t ant, uint32_t cur, int k,
                                   const Tabu& tabu, uint8_t* region, float tmin_a, int lane) {
     const int n = s.n;
-    const uint16_t* list;
-    int L;
-    if constexpr (kTabu == MMAS_TABU_BITMASK) {
-        uint16_t* ulist = reinterpret_cast<uint16_t*>(region + kDrawBytes + kScratchBytes + align16(4 * ((n + 31) / 32)));
-        L = gather_unvisited(tabu, n, ulist, reinterpret_cast<uint32_t*>(region + kDrawBytes), lane);
-        list = ulist;
-    } else {
-        L = tabu.L;
-        list = tabu.entries;
-    }
     if constexpr (kPher == MMAS_PHER_DENSE) {
         const DenseWeight wt{vw.choice + (size_t)cur * n};
-        return fallback_list(list, L, wt, s.cl, s.seed, it, ant, (uint32_t)k, lane);
+        if constexpr (kTabu == MMAS_TABU_BITMASK) {
+            uint16_t* ulist = reinterpret_cast<uint16_t*>(region + kDrawBytes + kScratchBytes + align16(4 * ((n + 31) / 32)));
+            return fallback_bitmask(tabu, n, ulist, list_cap(s), wt, s.cl, s.seed, it, ant, (uint32_t)k, lane);
+        } else {
+            return fallback_list(tabu.entries, tabu.L, wt, s.cl, s.seed, it, ant, (uint32_t)k, lane);
+        }
     } else {
         const CandWeight wt{vw.dist + (size_t)cur * n, tmin_a, s.beta};
-        return fallback_list(list, L, wt, s.cl, s.seed, it, ant, (uint32_t)k, lane);
+        if constexpr (kTabu == MMAS_TABU_BITMASK) {
+            uint16_t* ulist = reinterpret_cast<uint16_t*>(region + kDrawBytes + kScratchBytes + align16(4 * ((n + 31) / 32)));
+            return fallback_bitmask(tabu, n, ulist, list_cap(s), wt, s.cl, s.seed, it, ant, (uint32_t)k, lane);
+        } else {
+            return fallback_list(tabu.entries, tabu.L, wt, s.cl, s.seed, it, ant, (uint32_t)k, lane);
+        }
     }
 }
 
@@ -774,7 +813,11 @@ namespace {
 bool pair_ok(const Shape& s) { return s.lanes_per_ant == 32 && s.cl >= 1 && s.cl <= 32; }
 
 template <int kTabu, int kPher, bool kPair>
-hipError_t launch_t(const Views& v, const Shape& s, uint32_t it, hipStream_t st) {
+hipError_t launch_t(const Views& v, const Shape& s0, uint32_t it, hipStream_t st) {
+    // one colony: a workgroup per four ants rarely shares a CU, so the fallback
+    // lists every unvisited city in one pass
+    Shape s = s0;
+    s.list_cap = s.n;
     const int per_ant = (int)construct_lds_per_ant(s);
     const int budget = max_lds_per_block();
     int apb = s.ants_per_block > 0 ? s.ants_per_block : 4;
@@ -820,7 +863,7 @@ int construct_waves(const Shape& s) {
 
 template <int kTabu, int kPher>
 hipError_t launch_wide(const Views& v, const Shape& s, uint32_t it, int waves, hipStream_t st) {
-    const int per_ant = (int)construct_lds_per_ant(s);
+    const int per_ant = (int)wide_lds_per_ant(s);
     const int budget = max_lds_per_block() - (int)sizeof(WideLds) - 64;
     if (per_ant > budget) return hipErrorInvalidValue;
     Lds lds{};
@@ -874,6 +917,12 @@ const void* batch_kernel(int tabu, int pher, bool pair) {
 size_t construct_lds_per_ant(const Shape& s) {
     // draws; tabu (bitmask words, or compact entries); for the bitmask, the
     // list of unvisited cities built in a fallback
+    const int bits = align16(4 * ((s.n + 31) / 32));
+    return kDrawBytes + kScratchBytes + (s.tabu == MMAS_TABU_BITMASK ? bits + align16(2 * list_cap(s)) : align16(2 * s.n));
+}
+
+size_t wide_lds_per_ant(const Shape& s) {
+    // as construct_lds_per_ant, with room to list every unvisited city at once
     const int bits = align16(4 * ((s.n + 31) / 32));
     const int list = align16(2 * s.n);
     return kDrawBytes + kScratchBytes + (s.tabu == MMAS_TABU_BITMASK ? bits + list : list);

@@ -46,6 +46,8 @@ struct Shape {
     int lanes_per_ant;   // construction launch: 64 (one ant per wave) or 32 (two)
     int construct_waves; // construction launch: waves per ant (0 = from the ant count)
     int table_rows;      // rows of the candidate table staged in LDS (-1: all that fit)
+    int list_cap;        // construction: entries of a bitmask fallback's city list
+                         // (0: min(n, kListCap); the launcher may raise it to n)
     int two_opt_waves;   // 2-opt launch: waves per ant (1..16)
 };
 
@@ -114,8 +116,10 @@ hipError_t launch_install(const int32_t* dist, const uint16_t* knn, const float*
                           int beta, int dense, float* heur, hipStream_t st);
 hipError_t launch_labels(const uint16_t* tours, int R, int n, const uint16_t* knn, float* label, hipStream_t st);
 
-// LDS bytes one ant needs in the construction kernel (0 if it cannot run).
+// LDS bytes one ant needs in the construction kernels with one wave (or half
+// a wave) per ant, and with several waves per ant.
 size_t construct_lds_per_ant(const Shape& s);
+size_t wide_lds_per_ant(const Shape& s);
 // LDS bytes of the 2-opt kernel (one tour per workgroup).
 size_t two_opt_lds_bytes(const Shape& s, bool with_len);
 // LDS the 2-opt kernel declares statically (city list, per-wave records)

@@ -164,7 +164,7 @@ mmas_status mmas_create(const int32_t* dist_host, const mmas_params* p, void* de
             delete c;
             return mmas::hip_fail(e, "device query");
         }
-        if (mmas::construct_lds_per_ant(s) > (size_t)maxlds ||
+        if (mmas::wide_lds_per_ant(s) > (size_t)maxlds ||
             (s.ls_nn > 0 && mmas::two_opt_lds_bytes(s, false) + mmas::kTwoOptStaticLds > (size_t)maxlds)) {
             delete c;
             return MMAS_EUNSUPPORTED;

@@ -36,20 +36,6 @@ struct Cand {
                              // bit 4: the edge left of position i becomes {a, c}
 };
 
-// Inclusive prefix sum over the wave: row scans by DPP, row totals by readlane.
-__device__ __forceinline__ int wave_incl_scan(int x, int lane) {
-    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
-    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
-    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
-    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
-    const int r0 = __builtin_amdgcn_readlane(x, 15);
-    const int r1 = __builtin_amdgcn_readlane(x, 31);
-    const int r2 = __builtin_amdgcn_readlane(x, 47);
-    const int row = lane >> 4;
-    x += (row >= 1 ? r0 : 0) + (row >= 2 ? r1 : 0) + (row >= 3 ? r2 : 0);
-    return x;
-}
-
 __device__ __forceinline__ uint32_t dlb_bit(const uint32_t* dlb, int x) { return (dlb[x >> 5] >> (x & 31)) & 1u; }
 
 // The next `count` active cities (don't-look bit clear) from city a0,
