@@ -743,7 +743,10 @@ __global__ __launch_bounds__(1024) void k_construct_wide(Views vw, Shape s, uint
 // tile stages as many candidate rows of its instance as fit in the table part
 // of LDS, then every wave builds one ant's tour (two with kPair).
 template <int kTabu, int kPher, bool kPair>
-__global__ __launch_bounds__(1024) void k_batch_construct(const BatchItem* __restrict__ items,
+// (limited to 64 VGPRs, which lets eight waves share a SIMD: the persistent
+// batch is bound by instruction issue, and the extra waves hide more latency
+// than the few spilled registers cost)
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_batch_construct(const BatchItem* __restrict__ items,
                                                           const BatchTile* __restrict__ tiles, int ntiles,
                                                           uint32_t* __restrict__ queue, const uint32_t* __restrict__ it_dev,
                                                           int ants_per_block, int table_bytes, int per_ant) {

@@ -118,3 +118,38 @@ def test_graph_replays_match_eager(gpu):
             assert np.array_equal(v.tours(), ref[i][it][0]), (it, i)
             assert np.array_equal(v.pheromone(), ref[i][it][1]), (it, i)
         assert b.iteration() == it + 1
+
+
+def test_fallback_list_in_passes(gpu):
+    """The batched kernel lists a bitmask fallback's unvisited cities in passes
+    of at most 512; with short candidate lists on instances of 600-1500 cities
+    many fallbacks see more than 512 unvisited cities and take several passes.
+    Tours and trails equal those of single contexts (one full list) and, for
+    one instance, the oracle's."""
+    from oracle import oracle as O
+    from paper_2003_11902_amd import mmas as M
+    dists, params = [], []
+    for k, n in enumerate((600, 1100, 1500)):
+        _, d = I.make_instance("uniform" if k != 1 else "clustered", n, seed=500 + k,
+                               **({} if k != 1 else dict(clusters=6, sigma=300.0)))
+        dists.append(d)
+        params.append(M.make_params(n, 24, cand_len=4, rho=0.05, seed=2000 + k))
+    say("batch fallback passes: n 600/1100/1500, cl 4")
+    ref = singles(dists, params, 2)
+    b = M.Batch(dists, params)
+    for it in range(2):
+        b.step()
+        b.synchronize()
+        for i in range(len(dists)):
+            v = b.instance(i)
+            assert np.array_equal(v.tours(), ref[i][it][0]), (it, i)
+            assert np.array_equal(v.pheromone(), ref[i][it][1]), (it, i)
+    # some fallback saw more than 512 unvisited cities: the fallback steps of
+    # an ant are distinct steps k, so if every one had n - k <= 512, their
+    # unvisited counts would sum to at most 512 + 511 + ... (steps terms)
+    steps, nodes = b.instance(2).fallback()
+    assert (nodes > steps * 512 - steps * (steps - 1) // 2).any()
+    o = O.Colony(dists[2], 24, cand_len=4, rho=0.05, seed=2002)
+    for it in range(2):
+        o.iterate(it, 8)
+    assert np.array_equal(b.instance(2).tours(), o.tours())
