@@ -145,7 +145,9 @@ mmas_status mmas_construct(mmas_ctx* ctx, uint32_t iteration);
  * `ants_per_block`: ants per workgroup, 1, 2, 4, 8 or 16 (0 = default 4;
  * fewer are used if their LDS does not fit). `table_rows`: how many rows of
  * the candidate table (ids and choice_info) each workgroup stages in LDS:
- * -1 = as many as fit (default), 0 = none, k = at most k. `lanes_per_ant`:
+ * -1 = as many as fit (default; when the grid needs several workgroups per
+ * CU, as many as fit in one workgroup's share of the CU's LDS), 0 = none,
+ * k = at most k. `lanes_per_ant`:
  * 64 (one ant per wave64, default, also for 0) or 32 (two ants per wave64,
  * each on a half; applies when 1 <= cand_len <= 32, with an even number of
  * ants per workgroup, else 64 is used). `waves_per_ant`: 1, 2, 4, 8 or 16
