@@ -11,6 +11,7 @@
 // four consecutive k), the B operand is B[4q .. 4q+3][c] (column c), and the
 // result holds D[4q + t][c], t = 0..3.
 #include <cmath>
+#include <cstddef>
 
 #include "device.hpp"
 #include "internal.hpp"
@@ -159,18 +160,21 @@ __global__ __launch_bounds__(256) void k_pack(const float* __restrict__ p, uint1
 
 // ---- forward / backward tiles -------------------------------------------------------
 
+// (the forward kernel allocates only the part before w2n: 55 KB, two
+// workgroups per CU; the fused training kernel all of it)
 struct Smem {
     uint16_t w1t[kHid * kIn];
     uint16_t w2t[kHid * kHid];
-    uint16_t w2n[kHid * kHid];
     uint16_t w3[kHid];
     float b1[kHid], b2[kHid];
     uint16_t x[64 * kIn];     // tile of 64 edges
     uint16_t h1[64 * kHid];
+    uint16_t w2n[kHid * kHid];
     uint16_t dz2[64 * kHid];
     uint16_t dz1[64 * kHid];
     float red[4][3 * kHid + 2];
 };
+constexpr size_t kForwardSmem = offsetof(Smem, w2n);
 
 __device__ void load_weights(Smem& sm, const float* __restrict__ p, const uint16_t* __restrict__ pk, bool need_w2n) {
     for (int t = threadIdx.x; t < kHid * kIn; t += blockDim.x) sm.w1t[t] = pk[kPkW1t + t];
@@ -513,23 +517,23 @@ hipError_t launch_pack(const float* p, uint16_t* pk, hipStream_t st) {
     return hipGetLastError();
 }
 
-static hipError_t smem_attr(const void* k) {
-    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Smem));
+static hipError_t smem_attr(const void* k, size_t bytes) {
+    return hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 hipError_t launch_mlp_forward(const uint16_t* X, const float* p, const uint16_t* pk, int64_t E, float* s,
                               hipStream_t st) {
-    hipError_t e = smem_attr((const void*)k_mlp_forward);
+    hipError_t e = smem_attr((const void*)k_mlp_forward, kForwardSmem);
     if (e != hipSuccess) return e;
     const int64_t tiles = (E + 63) / 64;
     const int grid = (int)(tiles < 2048 ? tiles : 2048);
-    k_mlp_forward<<<grid < 1 ? 1 : grid, 256, sizeof(Smem), st>>>(X, p, pk, E, s);
+    k_mlp_forward<<<grid < 1 ? 1 : grid, 256, kForwardSmem, st>>>(X, p, pk, E, s);
     return hipGetLastError();
 }
 
 hipError_t launch_mlp_train(const uint16_t* X, const float* f, const float* p, const uint16_t* pk, int64_t E,
                             float* partial, int groups, float* grad, hipStream_t st) {
-    hipError_t e = smem_attr((const void*)k_mlp_train);
+    hipError_t e = smem_attr((const void*)k_mlp_train, sizeof(Smem));
     if (e != hipSuccess) return e;
     k_mlp_train<<<groups, 256, sizeof(Smem), st>>>(X, f, p, pk, E, partial);
     if ((e = hipGetLastError()) != hipSuccess) return e;
