@@ -154,7 +154,7 @@ def run_batched(args):
                    "n_range": [int(min(d.shape[0] for d in dists)), int(max(d.shape[0] for d in dists))],
                    "ants": "n per instance" if not args.batch_of else int(params[0].ants),
                    "cand_len": int(params[0].cand_len), "rho": float(params[0].rho),
-                   "tabu": {0: "bitmask", 1: "compact"}[tuned_tabu], "graph": not args.no_graph, "ants_per_block": apb, "table_bytes": tb, "lanes_per_ant": lanes,
+                   "tabu": {0: "bitmask", 1: "compact", 2: "list"}[tuned_tabu], "graph": not args.no_graph, "ants_per_block": apb, "table_bytes": tb, "lanes_per_ant": lanes,
                    "total_ants": total_ants},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -169,7 +169,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="clustered1002")
-    ap.add_argument("--tabu", default="bitmask", choices=["bitmask", "compact"])
+    ap.add_argument("--tabu", default="bitmask", choices=["bitmask", "compact", "list"])
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--ants", type=int, default=0, help="override the workload's ant count")
     ap.add_argument("--ants-per-block", type=int, default=0)

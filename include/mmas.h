@@ -46,7 +46,9 @@ typedef enum mmas_status {
     MMAS_ESTATE = -5       /* call out of order (e.g. update before construct) */
 } mmas_status;
 
-enum { MMAS_TABU_BITMASK = 0, MMAS_TABU_COMPACT = 1 };
+/* Tabu (visited set) of an ant in LDS, Sec. 4.1: a bitmask (n/8 bytes), the
+ * compact tabu (2n bytes) or the list tabu (4n bytes); tours never depend on it. */
+enum { MMAS_TABU_BITMASK = 0, MMAS_TABU_COMPACT = 1, MMAS_TABU_LIST = 2 };
 enum { MMAS_PHER_DENSE = 0, MMAS_PHER_CANDIDATES = 1 };
 
 /* Run parameters. Sec. 5 lists the paper's settings (m = n ants, alpha = 1,
@@ -62,7 +64,7 @@ typedef struct mmas_params {
     float rho;         /* evaporation rate in (0,1): tau <- max((1-rho) tau, tau_min) */
     double p_best;     /* (0,1): probability of rebuilding the best tour once converged */
     uint64_t seed;     /* Philox key */
-    int32_t tabu;      /* MMAS_TABU_BITMASK or MMAS_TABU_COMPACT */
+    int32_t tabu;      /* MMAS_TABU_BITMASK, MMAS_TABU_COMPACT or MMAS_TABU_LIST */
     int32_t pher_mode; /* MMAS_PHER_DENSE: n*n trails; MMAS_PHER_CANDIDATES: trails
                           stored only on the (i, cand[i][r]) edges, every other edge
                           held at tau_min (needs cand_len >= 1) */
@@ -232,7 +234,7 @@ mmas_status mmas_batch_create(int32_t count, const int32_t* const* dists_host, c
 mmas_status mmas_batch_set_launch(mmas_batch* b, int32_t ants_per_block, int32_t table_bytes,
                                   int32_t lanes_per_ant);
 
-/* Tabu of the batch's constructions, MMAS_TABU_BITMASK or MMAS_TABU_COMPACT
+/* Tabu of the batch's constructions, MMAS_TABU_BITMASK, _COMPACT or _LIST
  * (tours never depend on it); keeps the launch shape, EUNSUPPORTED if that
  * shape's LDS no longer fits. Drops a captured graph. */
 mmas_status mmas_batch_set_tabu(mmas_batch* b, int32_t tabu);
@@ -329,6 +331,17 @@ mmas_status mmas_eval_log(const float* dev_u, float* dev_out, size_t count, void
 mmas_status mmas_eval_draws(uint64_t seed, const uint32_t* dev_it, const uint32_t* dev_ant,
                             const uint32_t* dev_step, const uint32_t* dev_slot, uint32_t* dev_out,
                             size_t count, void* hip_stream);
+
+/* The construction's tabu (Sec. 4.1) on its own: one wave marks the cities
+ * dev_marks[0 .. count) in order in a fresh tabu of type `tabu` for n cities
+ * (1 <= n <= 8192, count <= n) and writes dev_visited[v] (n bytes, 0/1), the
+ * tabu's cells to dev_state (bitmask: ceil(n/32) words as pairs of 16-bit
+ * halves, low half first; compact: entries, n values; list: unv then idx, 2n
+ * values) and to *dev_left the number of unvisited cities, or -1 if a mark
+ * was out of range or already marked (marking stops there). Device arrays;
+ * enqueues on `hip_stream`. EINVAL for other arguments. */
+mmas_status mmas_eval_tabu(int32_t tabu, int32_t n, const int32_t* dev_marks, int32_t count,
+                           uint8_t* dev_visited, uint16_t* dev_state, int32_t* dev_left, void* hip_stream);
 
 /* Text of the HIP error behind the calling thread's last MMAS_EHIP (which
  * step failed and HIP's message); "" if none. */

@@ -34,7 +34,7 @@ struct mmas_batch {
     int max_tiles;
     int tabu, pher;
     int per_ant;        // largest per-ant LDS region over the instances (current tabu)
-    int per_ant_tabu[2];  // the same for the bitmask and the compact tabu
+    int per_ant_tabu[3];  // the same for the bitmask, the compact and the list tabu
     int table_request;  // table_bytes as last asked for (-1: all that fits)
     int ants_per_block;
     int lanes_per_ant;
@@ -173,7 +173,7 @@ mmas_status mmas_batch_create(int32_t count, const int32_t* const* dists_host, c
     b->items.resize(count);
     std::vector<int> row_start(count + 1, 0);
     b->per_ant = 0;
-    b->per_ant_tabu[0] = b->per_ant_tabu[1] = 0;
+    b->per_ant_tabu[0] = b->per_ant_tabu[1] = b->per_ant_tabu[2] = 0;
     for (int i = 0; i < count; ++i) {
         const size_t w = mmas_workspace_bytes(&params[i]);
         r = mmas_create(dists_host[i], &params[i], b->ws + pos, w, hip_stream, &b->ctx[i]);
@@ -187,7 +187,7 @@ mmas_status mmas_batch_create(int32_t count, const int32_t* const* dists_host, c
         mmas::ctx_views(b->ctx[i], &b->items[i].v, &b->items[i].s);
         row_start[i + 1] = row_start[i] + b->items[i].s.n;
         b->per_ant = std::max(b->per_ant, (int)mmas::construct_lds_per_ant(b->items[i].s));
-        for (int t = 0; t < 2; ++t) {
+        for (int t = 0; t < 3; ++t) {
             mmas::Shape st = b->items[i].s;
             st.tabu = t;
             b->per_ant_tabu[t] = std::max(b->per_ant_tabu[t], (int)mmas::construct_lds_per_ant(st));
@@ -246,7 +246,7 @@ mmas_status mmas_batch_set_launch(mmas_batch* b, int32_t ants_per_block, int32_t
 }
 
 mmas_status mmas_batch_set_tabu(mmas_batch* b, int32_t tabu) {
-    if (!b || (tabu != MMAS_TABU_BITMASK && tabu != MMAS_TABU_COMPACT)) return MMAS_EINVAL;
+    if (!b || (tabu != MMAS_TABU_BITMASK && tabu != MMAS_TABU_COMPACT && tabu != MMAS_TABU_LIST)) return MMAS_EINVAL;
     const int keep = b->tabu;
     apply_tabu(b, tabu);
     mmas_status r = mmas_batch_set_launch(b, b->ants_per_block, b->table_request, b->lanes_per_ant);

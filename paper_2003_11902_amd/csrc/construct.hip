@@ -66,6 +66,7 @@ struct CompactTabu {
         for (int i = lane; i < n_; i += kWave) entries[i] = (uint16_t)i;
     }
     __device__ __forceinline__ bool visited(uint32_t v) const { return entries[v] > v; }
+    __device__ __forceinline__ const uint16_t* list() const { return entries; }  // the L unvisited cities
     __device__ __forceinline__ void mark(uint32_t u, int lane) {
         // every lane reads the same cells; lane 0 writes
         const int iu = entries[u];  // position of u in the left part
@@ -79,6 +80,43 @@ struct CompactTabu {
                 entries[t] = (uint16_t)iu;
             }
             if ((int)u != iu) entries[u] = (uint16_t)n;
+        }
+    }
+};
+
+// The list tabu of Sec. 4.1 (after Dawson and Stewart, and Uchida et al.):
+// unv[0 .. L) lists the unvisited cities, idx[v] is the position of city v
+// in unv; marking v swaps it with the last unvisited entry and shortens the
+// list (reading C-18: the swap that the worked example of Sec. 4.1 needs), so
+// city v is visited iff idx[v] >= L. 4n bytes.
+struct ListTabu {
+    uint16_t* unv;
+    uint16_t* idx;
+    int L;
+    __device__ void attach(uint8_t* lds, int n_) {
+        unv = reinterpret_cast<uint16_t*>(lds);
+        idx = unv + n_;
+        L = n_;
+    }
+    __device__ void init(uint8_t* lds, int n_, int lane) {
+        attach(lds, n_);
+        for (int i = lane; i < n_; i += kWave) {
+            unv[i] = (uint16_t)i;
+            idx[i] = (uint16_t)i;
+        }
+    }
+    __device__ __forceinline__ bool visited(uint32_t v) const { return (int)idx[v] >= L; }
+    __device__ __forceinline__ const uint16_t* list() const { return unv; }
+    __device__ __forceinline__ void mark(uint32_t u, int lane) {
+        // every lane reads the same cells; lane 0 writes
+        const int iu = idx[u];
+        L = L - 1;
+        const int last = unv[L];
+        if (lane == 0) {
+            unv[iu] = (uint16_t)last;
+            idx[last] = (uint16_t)iu;
+            unv[L] = (uint16_t)u;
+            idx[u] = (uint16_t)L;
         }
     }
 };
@@ -108,6 +146,10 @@ struct TabuOf<MMAS_TABU_BITMASK> {
 template <>
 struct TabuOf<MMAS_TABU_COMPACT> {
     using type = CompactTabu;
+};
+template <>
+struct TabuOf<MMAS_TABU_LIST> {
+    using type = ListTabu;
 };
 
 __device__ __forceinline__ void keep_best(uint32_t code, uint32_t node, uint32_t& bcode, uint32_t& bnode) {
@@ -432,7 +474,7 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
                     list = ulist;
                 } else {
                     L = wl->L;
-                    list = tabu.entries;
+                    list = tabu.list();
                 }
                 unsigned long long mine;
                 if constexpr (kPher == MMAS_PHER_DENSE) {
@@ -468,16 +510,16 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
                     next = kOutline ? fallback_bitmask_call(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane)
                                     : fallback_bitmask(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
                 else
-                    next = kOutline ? fallback_list_call(tabu.entries, tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane)
-                                    : fallback_list(tabu.entries, tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+                    next = kOutline ? fallback_list_call(tabu.list(), tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane)
+                                    : fallback_list(tabu.list(), tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
             } else {
                 const CandWeight wt{dist + (size_t)cur * n, tmin_a, s.beta};
                 if constexpr (kTabu == MMAS_TABU_BITMASK)
                     next = kOutline ? fallback_bitmask_call(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane)
                                     : fallback_bitmask(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
                 else
-                    next = kOutline ? fallback_list_call(tabu.entries, tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane)
-                                    : fallback_list(tabu.entries, tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+                    next = kOutline ? fallback_list_call(tabu.list(), tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane)
+                                    : fallback_list(tabu.list(), tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
             }
         }
         if (next >= (uint32_t)n) {
@@ -543,7 +585,7 @@ __device__ uint32_t fallback_step(const Views& vw, const Shape& s, uint32_t it, 
             uint16_t* ulist = reinterpret_cast<uint16_t*>(region + kDrawBytes + kScratchBytes + align16(4 * ((n + 31) / 32)));
             return fallback_bitmask(tabu, n, ulist, list_cap(s), wt, s.cl, s.seed, it, ant, (uint32_t)k, lane);
         } else {
-            return fallback_list(tabu.entries, tabu.L, wt, s.cl, s.seed, it, ant, (uint32_t)k, lane);
+            return fallback_list(tabu.list(), tabu.L, wt, s.cl, s.seed, it, ant, (uint32_t)k, lane);
         }
     } else {
         const CandWeight wt{vw.dist + (size_t)cur * n, tmin_a, s.beta};
@@ -551,7 +593,7 @@ __device__ uint32_t fallback_step(const Views& vw, const Shape& s, uint32_t it, 
             uint16_t* ulist = reinterpret_cast<uint16_t*>(region + kDrawBytes + kScratchBytes + align16(4 * ((n + 31) / 32)));
             return fallback_bitmask(tabu, n, ulist, list_cap(s), wt, s.cl, s.seed, it, ant, (uint32_t)k, lane);
         } else {
-            return fallback_list(tabu.entries, tabu.L, wt, s.cl, s.seed, it, ant, (uint32_t)k, lane);
+            return fallback_list(tabu.list(), tabu.L, wt, s.cl, s.seed, it, ant, (uint32_t)k, lane);
         }
     }
 }
@@ -921,11 +963,18 @@ const void* batch_kernel(int tabu, int pher, bool pair) {
         return pair ? (const void*)k_batch_construct<MMAS_TABU_BITMASK, MMAS_PHER_CANDIDATES, true>
                     : (const void*)k_batch_construct<MMAS_TABU_BITMASK, MMAS_PHER_CANDIDATES, false>;
     }
+    if (tabu == MMAS_TABU_COMPACT) {
+        if (pher == MMAS_PHER_DENSE)
+            return pair ? (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_DENSE, true>
+                        : (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_DENSE, false>;
+        return pair ? (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_CANDIDATES, true>
+                    : (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_CANDIDATES, false>;
+    }
     if (pher == MMAS_PHER_DENSE)
-        return pair ? (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_DENSE, true>
-                    : (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_DENSE, false>;
-    return pair ? (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_CANDIDATES, true>
-                : (const void*)k_batch_construct<MMAS_TABU_COMPACT, MMAS_PHER_CANDIDATES, false>;
+        return pair ? (const void*)k_batch_construct<MMAS_TABU_LIST, MMAS_PHER_DENSE, true>
+                    : (const void*)k_batch_construct<MMAS_TABU_LIST, MMAS_PHER_DENSE, false>;
+    return pair ? (const void*)k_batch_construct<MMAS_TABU_LIST, MMAS_PHER_CANDIDATES, true>
+                : (const void*)k_batch_construct<MMAS_TABU_LIST, MMAS_PHER_CANDIDATES, false>;
 }
 
 }  // namespace
@@ -934,14 +983,17 @@ size_t construct_lds_per_ant(const Shape& s) {
     // draws; tabu (bitmask words, or compact entries); for the bitmask, the
     // list of unvisited cities built in a fallback
     const int bits = align16(4 * ((s.n + 31) / 32));
-    return kDrawBytes + kScratchBytes + (s.tabu == MMAS_TABU_BITMASK ? bits + align16(2 * list_cap(s)) : align16(2 * s.n));
+    const int tab = s.tabu == MMAS_TABU_BITMASK ? bits + align16(2 * list_cap(s))
+                    : s.tabu == MMAS_TABU_COMPACT ? align16(2 * s.n) : align16(4 * s.n);
+    return kDrawBytes + kScratchBytes + tab;
 }
 
 size_t wide_lds_per_ant(const Shape& s) {
     // as construct_lds_per_ant, with room to list every unvisited city at once
     const int bits = align16(4 * ((s.n + 31) / 32));
     const int list = align16(2 * s.n);
-    return kDrawBytes + kScratchBytes + (s.tabu == MMAS_TABU_BITMASK ? bits + list : list);
+    const int tab = s.tabu == MMAS_TABU_BITMASK ? bits + list : s.tabu == MMAS_TABU_COMPACT ? list : align16(4 * s.n);
+    return kDrawBytes + kScratchBytes + tab;
 }
 
 hipError_t launch_batch_construct(const BatchItem* items, const BatchTile* tiles, int ntiles, uint32_t* queue,
@@ -977,13 +1029,73 @@ int batch_construct_grid(int tabu, int pher, int ants_per_block, int lanes_per_a
     return per_cu * cus;
 }
 
+namespace {
+
+// One wave marks marks[0 .. count) in a fresh tabu of n cities, in order, then
+// writes visited[v] for every city, the tabu's cells (bitmask: its 32-bit
+// words as pairs of 16-bit halves, low first; compact: entries[0 .. n); list:
+// unv[0 .. n) then idx[0 .. n)) and the unvisited count (-1 if a mark was out
+// of range or already visited: the marking stops there).
+template <int kTabu>
+__global__ __launch_bounds__(64) void k_eval_tabu(int n, const int32_t* __restrict__ marks, int count,
+                                                  uint8_t* __restrict__ visited, uint16_t* __restrict__ state,
+                                                  int32_t* __restrict__ left) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int lane = threadIdx.x;
+    typename TabuOf<kTabu>::type tabu;
+    tabu.init(smem, n, lane);
+    int bad = 0;
+    for (int q = 0; q < count; ++q) {
+        const int u = __builtin_amdgcn_readfirstlane(marks[q]);
+        if (u < 0 || u >= n || tabu.visited((uint32_t)u)) {
+            bad = 1;
+            break;
+        }
+        tabu.mark((uint32_t)u, lane);
+    }
+    for (int v = lane; v < n; v += kWave) visited[v] = tabu.visited((uint32_t)v) ? 1 : 0;
+    if constexpr (kTabu == MMAS_TABU_BITMASK) {
+        for (int w = lane; w < (n + 31) / 32; w += kWave) {
+            state[2 * w] = (uint16_t)(tabu.bits[w] & 0xFFFFu);
+            state[2 * w + 1] = (uint16_t)(tabu.bits[w] >> 16);
+        }
+    } else if constexpr (kTabu == MMAS_TABU_COMPACT) {
+        for (int v = lane; v < n; v += kWave) state[v] = tabu.entries[v];
+    } else {
+        for (int v = lane; v < n; v += kWave) {
+            state[v] = tabu.unv[v];
+            state[n + v] = tabu.idx[v];
+        }
+    }
+    if (lane == 0) *left = bad ? -1 : n - count;
+}
+
+}  // namespace
+
+hipError_t launch_eval_tabu(int tabu, int n, const int32_t* marks, int count, uint8_t* visited, uint16_t* state,
+                            int32_t* left, hipStream_t st) {
+    const size_t bytes = tabu == MMAS_TABU_BITMASK ? (size_t)align16(4 * ((n + 31) / 32))
+                                                   : (size_t)align16((tabu == MMAS_TABU_COMPACT ? 2 : 4) * n);
+    if (tabu == MMAS_TABU_BITMASK)
+        k_eval_tabu<MMAS_TABU_BITMASK><<<1, kWave, bytes, st>>>(n, marks, count, visited, state, left);
+    else if (tabu == MMAS_TABU_COMPACT)
+        k_eval_tabu<MMAS_TABU_COMPACT><<<1, kWave, bytes, st>>>(n, marks, count, visited, state, left);
+    else
+        k_eval_tabu<MMAS_TABU_LIST><<<1, kWave, bytes, st>>>(n, marks, count, visited, state, left);
+    return hipGetLastError();
+}
+
 hipError_t launch_construct(const Views& v, const Shape& s, uint32_t it, hipStream_t st) {
     if (s.tabu == MMAS_TABU_BITMASK) {
         return s.pher == MMAS_PHER_DENSE ? launch_tp<MMAS_TABU_BITMASK, MMAS_PHER_DENSE>(v, s, it, st)
                                          : launch_tp<MMAS_TABU_BITMASK, MMAS_PHER_CANDIDATES>(v, s, it, st);
     }
-    return s.pher == MMAS_PHER_DENSE ? launch_tp<MMAS_TABU_COMPACT, MMAS_PHER_DENSE>(v, s, it, st)
-                                     : launch_tp<MMAS_TABU_COMPACT, MMAS_PHER_CANDIDATES>(v, s, it, st);
+    if (s.tabu == MMAS_TABU_COMPACT) {
+        return s.pher == MMAS_PHER_DENSE ? launch_tp<MMAS_TABU_COMPACT, MMAS_PHER_DENSE>(v, s, it, st)
+                                         : launch_tp<MMAS_TABU_COMPACT, MMAS_PHER_CANDIDATES>(v, s, it, st);
+    }
+    return s.pher == MMAS_PHER_DENSE ? launch_tp<MMAS_TABU_LIST, MMAS_PHER_DENSE>(v, s, it, st)
+                                     : launch_tp<MMAS_TABU_LIST, MMAS_PHER_CANDIDATES>(v, s, it, st);
 }
 
 }  // namespace mmas

@@ -46,3 +46,15 @@ extern "C" mmas_status mmas_eval_draws(uint64_t seed, const uint32_t* dev_it, co
         seed, dev_it, dev_ant, dev_step, dev_slot, dev_out, count);
     return hipGetLastError() == hipSuccess ? MMAS_OK : MMAS_EHIP;
 }
+
+extern "C" mmas_status mmas_eval_tabu(int32_t tabu, int32_t n, const int32_t* dev_marks, int32_t count,
+                                      uint8_t* dev_visited, uint16_t* dev_state, int32_t* dev_left,
+                                      void* hip_stream) {
+    if (tabu != MMAS_TABU_BITMASK && tabu != MMAS_TABU_COMPACT && tabu != MMAS_TABU_LIST) return MMAS_EINVAL;
+    if (n < 1 || n > 8192 || count < 0 || count > n || (count > 0 && !dev_marks) || !dev_visited || !dev_state ||
+        !dev_left)
+        return MMAS_EINVAL;
+    const hipError_t e = mmas::launch_eval_tabu(tabu, n, dev_marks, count, dev_visited, dev_state, dev_left,
+                                                reinterpret_cast<hipStream_t>(hip_stream));
+    return e == hipSuccess ? MMAS_OK : mmas::hip_fail(e, "eval tabu");
+}

@@ -78,6 +78,9 @@ hipError_t launch_init_trails(const Views& v, const Shape& s, hipStream_t st);
 // ---- per iteration ----
 hipError_t launch_choice(const Views& v, const Shape& s, hipStream_t st);             // update.hip
 hipError_t launch_construct(const Views& v, const Shape& s, uint32_t it, hipStream_t st); // construct.hip
+// construct.hip: the tabu of one ant after some marks (diagnostics)
+hipError_t launch_eval_tabu(int tabu, int n, const int32_t* marks, int count, uint8_t* visited, uint16_t* state,
+                            int32_t* left, hipStream_t st);
 hipError_t launch_two_opt_prepare(const Views& v, const Shape& s, int32_t* nnd, hipStream_t st);  // two_opt.hip
 hipError_t launch_two_opt(const Views& v, const Shape& s, const int32_t* nnd, hipStream_t st);
 hipError_t launch_update(const Views& v, const Shape& s, hipStream_t st);            // update.hip

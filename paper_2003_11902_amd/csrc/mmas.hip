@@ -41,7 +41,7 @@ bool params_ok(const mmas_params* p) {
     if (p->alpha < 0 || p->alpha > 8 || p->beta < 0 || p->beta > 8) return false;
     if (!(p->rho > 0.0f && p->rho < 1.0f)) return false;
     if (!(p->p_best > 0.0 && p->p_best < 1.0)) return false;
-    if (p->tabu != MMAS_TABU_BITMASK && p->tabu != MMAS_TABU_COMPACT) return false;
+    if (p->tabu != MMAS_TABU_BITMASK && p->tabu != MMAS_TABU_COMPACT && p->tabu != MMAS_TABU_LIST) return false;
     if (p->pher_mode != MMAS_PHER_DENSE && p->pher_mode != MMAS_PHER_CANDIDATES) return false;
     const int cl = p->cand_len < p->n - 1 ? p->cand_len : p->n - 1;
     if (p->pher_mode == MMAS_PHER_CANDIDATES && cl == 0) return false;
@@ -156,7 +156,7 @@ mmas_status mmas_create(const int32_t* dist_host, const mmas_params* p, void* de
         delete c;
         return MMAS_ENOSPACE;
     }
-    if (s.tabu == MMAS_TABU_COMPACT || s.tabu == MMAS_TABU_BITMASK) {
+    {  // every tabu must fit in LDS (the list tabu takes 4n bytes per ant)
         int dev = 0, maxlds = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&maxlds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);

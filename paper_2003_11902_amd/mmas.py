@@ -26,6 +26,7 @@ MMAS_ESTATE = -5
 
 MMAS_TABU_BITMASK = 0
 MMAS_TABU_COMPACT = 1
+MMAS_TABU_LIST = 2
 MMAS_PHER_DENSE = 0
 MMAS_PHER_CANDIDATES = 1
 
@@ -43,14 +44,14 @@ MMAS_BUF_FALLBACK = 10
 MMAS_BUF_STATE = 11
 MMAS_BUF_LSNN = 12
 
-TABU = {"bitmask": MMAS_TABU_BITMASK, "compact": MMAS_TABU_COMPACT}
+TABU = {"bitmask": MMAS_TABU_BITMASK, "compact": MMAS_TABU_COMPACT, "list": MMAS_TABU_LIST}
 PHER = {"dense": MMAS_PHER_DENSE, "candidates": MMAS_PHER_CANDIDATES}
 
 EXPORTED = (
     "mmas_workspace_bytes", "mmas_create", "mmas_prepare_choice_info", "mmas_construct",
     "mmas_two_opt", "mmas_update_pheromone", "mmas_best", "mmas_buffer", "mmas_read",
     "mmas_set_pheromone", "mmas_synchronize", "mmas_destroy", "mmas_status_str",
-    "mmas_eval_log", "mmas_eval_draws", "mmas_set_launch",
+    "mmas_eval_log", "mmas_eval_draws", "mmas_eval_tabu", "mmas_set_launch",
     "mmas_batch_workspace_bytes", "mmas_batch_create", "mmas_batch_set_launch", "mmas_batch_tune",
     "mmas_batch_capture", "mmas_batch_step", "mmas_batch_iteration", "mmas_batch_context",
     "mmas_batch_destroy", "mmas_mlp_param_count", "mmas_mlp_packed_count", "mmas_mlp_features",
@@ -123,6 +124,8 @@ def _load():
     L.mmas_eval_log.restype = C.c_int
     L.mmas_eval_draws.argtypes = [C.c_uint64, p, p, p, p, p, C.c_size_t, p]
     L.mmas_eval_draws.restype = C.c_int
+    L.mmas_eval_tabu.argtypes = [C.c_int32, C.c_int32, p, C.c_int32, p, p, p, p]
+    L.mmas_eval_tabu.restype = C.c_int
     L.mmas_batch_workspace_bytes.argtypes = [C.c_int32, p, C.POINTER(C.c_size_t)]
     L.mmas_batch_workspace_bytes.restype = C.c_int
     L.mmas_batch_create.argtypes = [C.c_int32, p, p, p, C.c_size_t, p, C.POINTER(p)]
@@ -188,6 +191,27 @@ def mmas_eval_log(u):
     _check(lib.mmas_eval_log(C.c_void_p(u.data_ptr()), C.c_void_p(out.data_ptr()), u.numel(),
                              C.c_void_p(torch.cuda.current_stream().cuda_stream)), "mmas_eval_log")
     return out
+
+
+def mmas_eval_tabu(tabu, n, marks):
+    """The construction's tabu after marking the cities of the int32 CUDA
+    tensor `marks` in order: (visited uint8[n], cells uint16, unvisited count
+    or -1), as CPU numpy arrays / int."""
+    import torch
+
+    t = TABU.get(tabu, tabu)
+    dev = marks.device
+    words = (n + 31) // 32
+    cells = 2 * words if t == MMAS_TABU_BITMASK else (n if t == MMAS_TABU_COMPACT else 2 * n)
+    visited = torch.empty(n, dtype=torch.uint8, device=dev)
+    state = torch.empty(cells, dtype=torch.int16, device=dev)
+    left = torch.empty(1, dtype=torch.int32, device=dev)
+    _check(lib.mmas_eval_tabu(t, n, C.c_void_p(marks.data_ptr()) if marks.numel() else None, marks.numel(),
+                              C.c_void_p(visited.data_ptr()), C.c_void_p(state.data_ptr()),
+                              C.c_void_p(left.data_ptr()), C.c_void_p(torch.cuda.current_stream().cuda_stream)),
+           "mmas_eval_tabu")
+    torch.cuda.synchronize()
+    return visited.cpu().numpy(), state.cpu().numpy().view("uint16"), int(left.cpu()[0])
 
 
 def mmas_eval_draws(seed, it, ant, step, slot):

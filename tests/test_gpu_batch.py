@@ -39,7 +39,7 @@ def singles(dists, params, iterations):
     out = []
     for d, p in zip(dists, params):
         c = M.Colony(d, p.ants, cand_len=p.cand_len, alpha=p.alpha, beta=p.beta, rho=p.rho, seed=p.seed,
-                     tabu={0: "bitmask", 1: "compact"}[p.tabu])
+                     tabu={0: "bitmask", 1: "compact", 2: "list"}[p.tabu])
         hist = []
         for it in range(iterations):
             c.iterate(it)
@@ -48,7 +48,7 @@ def singles(dists, params, iterations):
     return out
 
 
-@pytest.mark.parametrize("tabu", ["bitmask", "compact"])
+@pytest.mark.parametrize("tabu", ["bitmask", "compact", "list"])
 def test_batch_equals_single_instances(gpu, tabu):
     from paper_2003_11902_amd import mmas as M
     dists, params = small_batch(tabu=tabu)
@@ -81,7 +81,7 @@ def test_launch_shapes_and_tuner_do_not_change_results(gpu):
         for i in range(len(dists)):
             assert np.array_equal(b.instance(i).tours(), ref[i][1][0]), (apb, tb, lanes, i)
             assert np.array_equal(b.instance(i).lengths(), ref[i][1][2]), (apb, tb, lanes, i)
-    for tabu in ("compact", "bitmask"):
+    for tabu in ("compact", "list", "bitmask"):
         say(f"tabu {tabu}")
         b = M.Batch(dists, params)
         b.set_tabu(tabu)

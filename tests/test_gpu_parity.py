@@ -93,7 +93,7 @@ def test_setup_parity(gpu, workload):
     assert np.array_equal(g.chc().view(np.uint32), o.chc().view(np.uint32))
 
 
-@pytest.mark.parametrize("tabu", ["bitmask", "compact"])
+@pytest.mark.parametrize("tabu", ["bitmask", "compact", "list"])
 def test_uniform198_full_run(gpu, tabu):
     """The n = 198 workload: 198 ants, cl 32, 20 iterations, every iteration."""
     xy, d, w = I.workload_instance("uniform198")
@@ -120,7 +120,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("tabu", ["bitmask", "compact"])
+@pytest.mark.parametrize("tabu", ["bitmask", "compact", "list"])
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_edge_cases(gpu, case, tabu):
     name, kind, n, seed, kw = case
@@ -132,7 +132,7 @@ def test_edge_cases(gpu, case, tabu):
     run_parity(d, 6, tabu=tabu, seed=seed, **kw)
 
 
-@pytest.mark.parametrize("tabu", ["bitmask", "compact"])
+@pytest.mark.parametrize("tabu", ["bitmask", "compact", "list"])
 def test_clustered1002_first_iterations(gpu, tabu):
     """The n = 1002 workload (1002 ants, cl 32), first 4 iterations."""
     xy, d, w = I.workload_instance("clustered1002")
@@ -146,7 +146,7 @@ def test_bitmask_equals_compact_and_repeatable(gpu):
     _, d = I.make_instance("clustered", 400, seed=21, clusters=6, sigma=300.0)
     from paper_2003_11902_amd import mmas as M
     runs = []
-    for tabu in ("bitmask", "compact", "bitmask"):
+    for tabu in ("bitmask", "compact", "list", "bitmask"):
         g = M.Colony(d, 200, cand_len=12, rho=0.05, seed=5, tabu=tabu)
         tours = []
         for it in range(5):
@@ -204,6 +204,9 @@ def test_error_paths(gpu):
     ((0, 40, 64, 8), "bitmask", "candidates", 16, 33),
     ((0, -1, 64, 16), "compact", "candidates", 5, 20),
     ((0, -1, 64, 16), "bitmask", "dense", 0, 20),  # every step is a fallback
+    ((4, -1, 64, 1), "list", "dense", 32, 101),
+    ((8, -1, 32, 0), "list", "candidates", 16, 64),
+    ((0, -1, 64, 8), "list", "dense", 0, 20),
     ((0, 0, 64, 0), "bitmask", "dense", 32, 101),  # waves from the ant count
 ])
 def test_launch_shapes_match_oracle(gpu, launch, tabu, pher, cl, ants):
