@@ -323,6 +323,7 @@ struct orc_colony {
     uint16_t* nn_tour;
     int64_t nn_len;
     int has_gb;
+    int deposit;      /* ORC_DEPOSIT_ITERATION_BEST or ORC_DEPOSIT_GLOBAL_BEST */
     int64_t gb_len;
     uint16_t* gb_tour;
     float tmin, tmax;
@@ -509,8 +510,10 @@ void orc_two_opt(orc_colony* c, int nthreads) {
 
 /* Alg. 1 after construction: iteration best; global best and limits if it
  * improved; evaporation tau <- max((1-rho) tau, tau_min); deposit of
- * 1/C_ib on both directions of the iteration best's edges; every stored
- * trail clamped to tau_max. */
+ * 1/C_ib on both directions of the iteration best's edges (or, with the
+ * global-best deposit that Sec. 2.1 allows, 1/C_gb on the global best's,
+ * the global best being updated first); every stored trail clamped to
+ * tau_max. */
 void orc_update(orc_colony* c) {
     int n = c->n, cl = c->cl;
     int ib = 0;
@@ -526,14 +529,16 @@ void orc_update(orc_colony* c) {
         memcpy(c->gb_tour, ibt, sizeof(uint16_t) * (size_t)n);
         orc_limits(c->rho, c->gb_len, n, c->pdec, &c->tmin, &c->tmax);
     }
+    const uint16_t* dep = c->deposit == ORC_DEPOSIT_GLOBAL_BEST ? c->gb_tour : ibt;
+    int64_t C_dep = c->deposit == ORC_DEPOSIT_GLOBAL_BEST ? c->gb_len : C_ib;
     int* succ = (int*)malloc(sizeof(int) * (size_t)n);
     int* pred = (int*)malloc(sizeof(int) * (size_t)n);
     for (int k = 0; k < n; ++k) {
-        succ[ibt[k]] = ibt[(k + 1) % n];
-        pred[ibt[(k + 1) % n]] = ibt[k];
+        succ[dep[k]] = dep[(k + 1) % n];
+        pred[dep[(k + 1) % n]] = dep[k];
     }
     float keep = 1.0f - c->rho;
-    float delta = (float)(1.0 / (double)C_ib);
+    float delta = (float)(1.0 / (double)C_dep);
     float tmin = c->tmin, tmax = c->tmax;
     if (c->pher_mode == ORC_PHER_DENSE) {
         for (int i = 0; i < n; ++i)
@@ -569,6 +574,11 @@ void orc_iterate(orc_colony* c, uint32_t it, int nthreads) {
 }
 
 /* ---- accessors ---- */
+int orc_set_deposit(orc_colony* c, int mode) {
+    if (mode != ORC_DEPOSIT_ITERATION_BEST && mode != ORC_DEPOSIT_GLOBAL_BEST) return -1;
+    c->deposit = mode;
+    return 0;
+}
 int orc_n(const orc_colony* c) { return c->n; }
 int orc_cl(const orc_colony* c) { return c->cl; }
 void orc_get_tours(const orc_colony* c, uint16_t* out) {

@@ -81,6 +81,11 @@ orc_colony* orc_create(int n, const int32_t* dist, int ants, int cand_len,
                        uint64_t seed, int pher_mode, int ls_nn);
 void orc_destroy(orc_colony* c);
 
+/* Whose tour deposits (Sec. 2.1): the iteration best (default) or the global
+ * best, which may replace it. Returns -1 for another mode. */
+enum { ORC_DEPOSIT_ITERATION_BEST = 0, ORC_DEPOSIT_GLOBAL_BEST = 1 };
+int orc_set_deposit(orc_colony* c, int mode);
+
 /* The per-iteration calls, in Alg. 1 order. */
 void orc_prepare_choice(orc_colony* c);              /* choice_info = tau^alpha * eta^beta */
 void orc_construct(orc_colony* c, uint32_t it, int nthreads); /* every ant builds a tour */

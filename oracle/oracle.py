@@ -44,6 +44,8 @@ def lib():
                                  C.c_double, C.c_uint64, C.c_int, C.c_int]
         L.orc_create.restype = p
         L.orc_destroy.argtypes = [p]
+        L.orc_set_deposit.argtypes = [p, C.c_int]
+        L.orc_set_deposit.restype = C.c_int
         L.orc_prepare_choice.argtypes = [p]
         L.orc_construct.argtypes = [p, C.c_uint32, C.c_int]
         L.orc_two_opt.argtypes = [p, C.c_int]
@@ -187,7 +189,7 @@ class Colony:
     """One oracle colony (Alg. 1 state for one instance)."""
 
     def __init__(self, dist, ants, cand_len=32, alpha=1, beta=2, rho=0.02, p_best=0.01,
-                 seed=1, pher_mode=PHER_DENSE, ls_nn=0):
+                 seed=1, pher_mode=PHER_DENSE, ls_nn=0, deposit=0):
         self.dist = np.ascontiguousarray(dist, dtype=np.int32)
         self.n = int(self.dist.shape[0])
         self.ants = int(ants)
@@ -197,6 +199,8 @@ class Colony:
                                    float(np.float32(rho)), self.pdec, seed, pher_mode, ls_nn)
         if not self._h:
             raise ValueError("orc_create rejected the arguments")
+        if lib().orc_set_deposit(self._h, {"iteration": 0, "global": 1}.get(deposit, deposit)) != 0:
+            raise ValueError("unknown deposit mode")
         self.cl = int(lib().orc_cl(self._h))
 
     def close(self):

@@ -137,3 +137,45 @@ def test_candidate_mode_update(orc, d60):
             if cand[i, r] in (succ[i], pred[i]):
                 v = np.float32(v + np.float32(1.0 / C))
             assert new[i, r] == min(v, tmax)
+
+
+def test_global_best_deposit(orc, d60):
+    """Sec. 2.1 lets the global best deposit instead of the iteration best: in
+    an iteration whose best is worse than the global best, exactly the global
+    best's 2n directed edges gain 1/C_gb (trails far from both limits), and
+    the global best itself is unchanged."""
+    n = 60
+    col = orc.Colony(d60, ants=6, cand_len=4, rho=0.1, seed=8, deposit="global")
+    col.iterate(0, nthreads=2)
+    gbt, C_gb = col.best()
+    for it in range(1, 40):
+        col.prepare_choice()
+        col.construct(it)
+        if col.lengths().min() > C_gb:
+            break
+        col.update()
+        gbt, C_gb = col.best()
+    else:
+        pytest.fail("no iteration with a worse iteration best")
+    tmin, tmax = orc.limits(0.1, int(C_gb), n, col.pdec)
+    rng = np.random.default_rng(2)
+    tau = rng.uniform(0.3, 0.6, size=(n, n)).astype(np.float32) * tmax
+    tau = np.minimum(tau, tau.T)
+    col.set_pheromone(tau)
+    ib_tour = col.tours()[int(np.argmin(col.lengths()))].copy()
+    col.update()
+    t2, C2 = col.best()
+    assert C2 == C_gb and np.array_equal(t2, gbt)
+    new = col.pheromone().astype(np.float64)
+    evap = ((np.float32(1.0) - np.float32(0.1)) * tau).astype(np.float64)
+    a, b = edges(gbt)
+    dep = np.zeros((n, n), bool)
+    dep[a, b] = True
+    dep[b, a] = True
+    assert np.array_equal(new[~dep], evap[~dep])
+    assert np.allclose(new[dep] - evap[dep], 1.0 / C_gb, rtol=1e-5)
+    # an edge of the iteration best that the global best lacks gets nothing
+    ia, ibb = edges(ib_tour)
+    only_ib = ~dep[ia, ibb]
+    assert only_ib.any()
+    assert np.array_equal(new[ia[only_ib], ibb[only_ib]], evap[ia[only_ib], ibb[only_ib]])
