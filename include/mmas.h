@@ -50,6 +50,9 @@ typedef enum mmas_status {
  * compact tabu (2n bytes) or the list tabu (4n bytes); tours never depend on it. */
 enum { MMAS_TABU_BITMASK = 0, MMAS_TABU_COMPACT = 1, MMAS_TABU_LIST = 2 };
 enum { MMAS_PHER_DENSE = 0, MMAS_PHER_CANDIDATES = 1 };
+/* Whose tour deposits in the update (Sec. 2.1): the iteration best, or the
+ * global best, which the paper allows instead. */
+enum { MMAS_DEPOSIT_ITERATION_BEST = 0, MMAS_DEPOSIT_GLOBAL_BEST = 1 };
 
 /* Run parameters. Sec. 5 lists the paper's settings (m = n ants, alpha = 1,
  * beta = 2, p_best = 0.01); Sec. 4.3 the candidate lists. */
@@ -70,7 +73,7 @@ typedef struct mmas_params {
                           held at tau_min (needs cand_len >= 1) */
     int32_t ls_nn;     /* 2-opt neighbour-list length 0..32 (the paper uses 32),
                           0 = no local search */
-    int32_t reserved;  /* must be 0 */
+    int32_t deposit;   /* MMAS_DEPOSIT_ITERATION_BEST (0) or MMAS_DEPOSIT_GLOBAL_BEST */
 } mmas_params;
 
 typedef struct mmas_ctx mmas_ctx;
@@ -177,7 +180,8 @@ mmas_status mmas_set_two_opt_launch(mmas_ctx* ctx, int32_t waves_per_ant);
  * lowest ant on ties); if it beats the global best (or there is none) it
  * becomes the global best and the limits are recomputed from its length;
  * then tau <- max(fl((1-rho) tau), tau_min), plus 1/C_ib on both directions
- * of the iteration best's edges, then min(., tau_max) on every stored trail;
+ * of the iteration best's edges (with MMAS_DEPOSIT_GLOBAL_BEST: 1/C_gb on
+ * the global best's), then min(., tau_max) on every stored trail;
  * choice_info is refreshed in the same pass. ESTATE before a construct. */
 mmas_status mmas_update_pheromone(mmas_ctx* ctx);
 

@@ -39,6 +39,7 @@ struct Shape {
     int ls_nn;
     int pher;    // MMAS_PHER_*
     int tabu;    // MMAS_TABU_*
+    int deposit; // MMAS_DEPOSIT_*
     float rho;
     double pdec; // p_best^(1/n)
     uint64_t seed;

@@ -46,7 +46,7 @@ bool params_ok(const mmas_params* p) {
     const int cl = p->cand_len < p->n - 1 ? p->cand_len : p->n - 1;
     if (p->pher_mode == MMAS_PHER_CANDIDATES && cl == 0) return false;
     if (p->ls_nn < 0 || p->ls_nn > 32 || p->ls_nn > p->n - 1) return false;
-    if (p->reserved != 0) return false;
+    if (p->deposit != MMAS_DEPOSIT_ITERATION_BEST && p->deposit != MMAS_DEPOSIT_GLOBAL_BEST) return false;
     return true;
 }
 
@@ -60,6 +60,7 @@ Shape shape_of(const mmas_params* p) {
     s.ls_nn = p->ls_nn;
     s.pher = p->pher_mode;
     s.tabu = p->tabu;
+    s.deposit = p->deposit;
     s.rho = p->rho;
     s.pdec = std::pow(p->p_best, 1.0 / (double)p->n);
     s.seed = p->seed;

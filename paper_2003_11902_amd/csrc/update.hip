@@ -36,7 +36,8 @@ __global__ __launch_bounds__(256) void k_choice_cand(const float* __restrict__ t
 // Iteration best = shortest tour, lowest ant on ties. If it beats the global
 // best (or there is none yet), it becomes the global best and the limits are
 // recomputed from its length. Then the successor and predecessor of every
-// city along the iteration best, for the deposit. One workgroup of any size
+// city along the tour that deposits: the iteration best, or the global best
+// (Sec. 2.1 allows either). One workgroup of any size
 // (a multiple of 64, at most 1024 threads).
 __device__ void best_and_limits(const Views& vw, const Shape& s) {
     __shared__ int64_t plen[16];
@@ -85,7 +86,7 @@ __device__ void best_and_limits(const Views& vw, const Shape& s) {
             st->tau_min = lo;
             st->tau_max = hi;
         }
-        st->delta = (float)(1.0 / (double)L);
+        st->delta = (float)(1.0 / (double)(s.deposit == MMAS_DEPOSIT_GLOBAL_BEST ? st->gb_len : L));
         st->updates += 1u;
         s_ib = a;
         s_improved = improved;
@@ -93,6 +94,15 @@ __device__ void best_and_limits(const Views& vw, const Shape& s) {
     __syncthreads();
     const uint16_t* t = vw.tours + (size_t)s_ib * s.n;
     const int n = s.n;
+    if (s.deposit == MMAS_DEPOSIT_GLOBAL_BEST && !s_improved) {
+        // the global best deposits and is unchanged: its stored tour
+        for (int k = threadIdx.x; k < n; k += blockDim.x) {
+            const uint16_t a = vw.gb_tour[k], b = vw.gb_tour[k + 1 == n ? 0 : k + 1];
+            vw.succ[a] = b;
+            vw.pred[b] = a;
+        }
+        return;
+    }
     for (int k = threadIdx.x; k < n; k += blockDim.x) {
         const uint16_t a = t[k], b = t[k + 1 == n ? 0 : k + 1];
         vw.succ[a] = b;

@@ -51,7 +51,7 @@ def test_workspace_bytes(M):
     dict(n=2), dict(n=65536), dict(ants=0), dict(cand_len=65), dict(cand_len=-1),
     dict(alpha=9), dict(beta=-1), dict(rho=0.0), dict(rho=1.0), dict(rho=float("nan")),
     dict(p_best=0.0), dict(p_best=1.0), dict(tabu=7), dict(pher=3),
-    dict(pher="candidates", cand_len=0), dict(ls_nn=33), dict(n=10, ls_nn=10),
+    dict(pher="candidates", cand_len=0), dict(ls_nn=33), dict(n=10, ls_nn=10), dict(deposit=2), dict(tabu=3),
 ])
 def test_invalid_params_give_zero_workspace(M, kw):
     args = dict(n=100, ants=10, cand_len=8)

@@ -216,3 +216,14 @@ def test_launch_shapes_match_oracle(gpu, launch, tabu, pher, cl, ants):
     _, d = I.make_instance("clustered", 230, seed=77, clusters=5, sigma=500.0)
     say(f"launch {launch} {tabu} {pher} cl={cl} ants={ants}")
     run_parity(d, 3, launch=launch, ants=ants, cand_len=cl, rho=0.05, seed=9, tabu=tabu, pher=pher)
+
+
+@pytest.mark.parametrize("pher", ["dense", "candidates"])
+def test_global_best_deposit(gpu, pher):
+    """The global-best deposit (Sec. 2.1): 25 iterations on 150 cities with few
+    ants, so that many iterations have an iteration best worse than the
+    global best; tours, lengths and trails equal the oracle's every
+    iteration."""
+    _, d = I.make_instance("clustered", 150, seed=31, clusters=5, sigma=400.0)
+    say(f"global-best deposit {pher}")
+    run_parity(d, 25, ants=6, cand_len=10, rho=0.1, seed=3, pher=pher, deposit="global")
