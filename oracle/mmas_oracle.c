@@ -324,6 +324,7 @@ struct orc_colony {
     int64_t nn_len;
     int has_gb;
     int deposit;      /* ORC_DEPOSIT_ITERATION_BEST or ORC_DEPOSIT_GLOBAL_BEST */
+    int select;       /* ORC_SELECT_WRS or ORC_SELECT_PRWM */
     int64_t gb_len;
     uint16_t* gb_tour;
     float tmin, tmax;
@@ -430,6 +431,97 @@ static float fallback_weight(const orc_colony* c, int cur, int v) {
     return powi_f32(c->tmin, c->alpha) * heur_of(c->dist[(size_t)cur * c->n + v], c->beta);
 }
 
+/* Inclusive prefix sums of 64 partial sums in the order a wave64 forms them:
+ * within each row of 16 a log-step scan (x[i] += x[i-d] for d = 1, 2, 4, 8,
+ * lanes below d of their row adding 0), then every row adds the totals of the
+ * rows before it (row 1: t0; row 2: t0 + t1; row 3: (t0 + t1) + t2). */
+static void scan64(float x[64]) {
+    for (int d = 1; d < 16; d <<= 1) {
+        float y[64];
+        for (int i = 0; i < 64; ++i) y[i] = (i % 16 >= d) ? x[i - d] : 0.0f;
+        for (int i = 0; i < 64; ++i) x[i] = x[i] + y[i];
+    }
+    float t0 = x[15], t1 = x[31], t2 = x[47];
+    for (int i = 0; i < 64; ++i) {
+        int row = i / 16;
+        float add = 0.0f;
+        if (row >= 1) add = t0;
+        if (row >= 2) add = add + t1;
+        if (row >= 3) add = add + t2;
+        x[i] = x[i] + add;
+    }
+}
+
+/* The parallel roulette wheel of Sec. 4.2.1 with p = 64: the m weights are
+ * cut into 64 chunks of ceil(m/64) (chunk sums left to right), the chunks'
+ * prefix sums are formed, u times the total is the target, and the first
+ * chunk whose prefix exceeds it wins (the last chunk with a positive sum if
+ * rounding leaves none); the target less the prefix before that chunk is
+ * then located in the same way inside it, until a chunk is one weight.
+ * Returns the winning index; m >= 1 and some weight > 0. */
+static int prwm_pick(const float* w, int m, float u) {
+    int lo = 0, len = m;
+    float target = 0.0f;
+    int first = 1;
+    for (;;) {
+        int c = (len + 63) / 64;
+        float s[64], P[64];
+        for (int l = 0; l < 64; ++l) {
+            float a = 0.0f;
+            for (int q = l * c; q < (l + 1) * c && q < len; ++q) a = a + w[lo + q];
+            s[l] = a;
+            P[l] = a;
+        }
+        scan64(P);
+        if (first) {
+            target = u * P[63];
+            first = 0;
+        }
+        int win = -1;
+        for (int l = 0; l < 64 && win < 0; ++l)
+            if (P[l] > target && s[l] > 0.0f) win = l;
+        for (int l = 63; l >= 0 && win < 0; --l)
+            if (s[l] > 0.0f) win = l;
+        if (win > 0) target = target - P[win - 1];
+        lo += win * c;
+        if (c == 1) return lo;
+        len = len - win * c < c ? len - win * c : c;
+    }
+}
+
+/* Node selection by the parallel roulette wheel (Sec. 4.2.1), the paper's
+ * baseline: one draw per step (slot 0); the wheel over the unvisited
+ * candidates by rank (visited ones weigh 0), or, when none is left, over
+ * every unvisited node in index order. */
+static int select_prwm(const orc_colony* c, int cur, const uint8_t* visited, uint32_t it, uint32_t ant,
+                       uint32_t step, int* fallback) {
+    int cl = c->cl, n = c->n;
+    float u = orc_u01(orc_draw_word(c->seed, it, ant, step, 0u));
+    float w[64];
+    int any = 0;
+    for (int r = 0; r < cl; ++r) {
+        int v = c->cand[(size_t)cur * cl + r];
+        w[r] = visited[v] ? 0.0f : c->chc[(size_t)cur * cl + r];
+        any |= !visited[v];
+    }
+    *fallback = 0;
+    if (any) return c->cand[(size_t)cur * cl + prwm_pick(w, cl, u)];
+    *fallback = 1;
+    int* list = (int*)malloc(sizeof(int) * (size_t)n);
+    float* wl = (float*)malloc(sizeof(float) * (size_t)n);
+    int L = 0;
+    for (int v = 0; v < n; ++v)
+        if (!visited[v]) {
+            list[L] = v;
+            wl[L] = fallback_weight(c, cur, v);
+            ++L;
+        }
+    int v = L > 0 ? list[prwm_pick(wl, L, u)] : -1;
+    free(list);
+    free(wl);
+    return v;
+}
+
 /* Node selection by weighted reservoir sampling (Alg. 4, Sec. 4.2.2): every
  * eligible node v draws u and gets the key ln(u)/w_v; the largest key wins
  * (a reservoir of size one); equal keys go to the lowest node index. The
@@ -437,6 +529,7 @@ static float fallback_weight(const orc_colony* c, int cur, int v) {
  * (Sec. 4.3); when it is empty, every unvisited node. */
 int orc_select_next(const orc_colony* c, int cur, const uint8_t* visited, uint32_t it, uint32_t ant,
                     uint32_t step, int* fallback) {
+    if (c->select == ORC_SELECT_PRWM) return select_prwm(c, cur, visited, it, ant, step, fallback);
     int cl = c->cl;
     int best = -1;
     float best_key = 0.0f;
@@ -574,6 +667,11 @@ void orc_iterate(orc_colony* c, uint32_t it, int nthreads) {
 }
 
 /* ---- accessors ---- */
+int orc_set_select(orc_colony* c, int mode) {
+    if (mode != ORC_SELECT_WRS && mode != ORC_SELECT_PRWM) return -1;
+    c->select = mode;
+    return 0;
+}
 int orc_set_deposit(orc_colony* c, int mode) {
     if (mode != ORC_DEPOSIT_ITERATION_BEST && mode != ORC_DEPOSIT_GLOBAL_BEST) return -1;
     c->deposit = mode;

@@ -86,6 +86,12 @@ void orc_destroy(orc_colony* c);
 enum { ORC_DEPOSIT_ITERATION_BEST = 0, ORC_DEPOSIT_GLOBAL_BEST = 1 };
 int orc_set_deposit(orc_colony* c, int mode);
 
+/* Node selection: weighted reservoir sampling (Alg. 4, default) or the
+ * parallel roulette wheel of Sec. 4.2.1 (64 chunks a stage, one draw per
+ * step). Returns -1 for another mode. */
+enum { ORC_SELECT_WRS = 0, ORC_SELECT_PRWM = 1 };
+int orc_set_select(orc_colony* c, int mode);
+
 /* The per-iteration calls, in Alg. 1 order. */
 void orc_prepare_choice(orc_colony* c);              /* choice_info = tau^alpha * eta^beta */
 void orc_construct(orc_colony* c, uint32_t it, int nthreads); /* every ant builds a tour */

@@ -46,6 +46,8 @@ def lib():
         L.orc_destroy.argtypes = [p]
         L.orc_set_deposit.argtypes = [p, C.c_int]
         L.orc_set_deposit.restype = C.c_int
+        L.orc_set_select.argtypes = [p, C.c_int]
+        L.orc_set_select.restype = C.c_int
         L.orc_prepare_choice.argtypes = [p]
         L.orc_construct.argtypes = [p, C.c_uint32, C.c_int]
         L.orc_two_opt.argtypes = [p, C.c_int]
@@ -189,7 +191,7 @@ class Colony:
     """One oracle colony (Alg. 1 state for one instance)."""
 
     def __init__(self, dist, ants, cand_len=32, alpha=1, beta=2, rho=0.02, p_best=0.01,
-                 seed=1, pher_mode=PHER_DENSE, ls_nn=0, deposit=0):
+                 seed=1, pher_mode=PHER_DENSE, ls_nn=0, deposit=0, select="wrs"):
         self.dist = np.ascontiguousarray(dist, dtype=np.int32)
         self.n = int(self.dist.shape[0])
         self.ants = int(ants)
@@ -201,6 +203,8 @@ class Colony:
             raise ValueError("orc_create rejected the arguments")
         if lib().orc_set_deposit(self._h, {"iteration": 0, "global": 1}.get(deposit, deposit)) != 0:
             raise ValueError("unknown deposit mode")
+        if lib().orc_set_select(self._h, {"wrs": 0, "prwm": 1}.get(select, select)) != 0:
+            raise ValueError("unknown selection")
         self.cl = int(lib().orc_cl(self._h))
 
     def close(self):

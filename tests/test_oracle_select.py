@@ -61,10 +61,11 @@ def test_candidates_match_sorted_rows(orc, inst):
     assert np.array_equal(orc.nearest(inst, 23).astype(np.int64), ref_candidates(inst, 23))
 
 
+@pytest.mark.parametrize("select", ["wrs", "prwm"])
 @pytest.mark.parametrize("kind", ["random", "geometric", "dominant"])
-def test_candidate_phase_frequencies(orc, inst, kind):
+def test_candidate_phase_frequencies(orc, inst, kind, select):
     n, cl = inst.shape[0], 8
-    col = orc.Colony(inst, ants=1, cand_len=cl, alpha=1, beta=2, seed=2024)
+    col = orc.Colony(inst, ants=1, cand_len=cl, alpha=1, beta=2, seed=2024, select=select)
     rng = np.random.default_rng(5)
     if kind == "random":
         tau = rng.uniform(0.1, 1.0, size=(n, n))
@@ -88,9 +89,10 @@ def test_candidate_phase_frequencies(orc, inst, kind):
     chi2_ok(counts, {k: v / tot for k, v in w.items()}, DRAWS)
 
 
-def test_fallback_frequencies_dense(orc, inst):
+@pytest.mark.parametrize("select", ["wrs", "prwm"])
+def test_fallback_frequencies_dense(orc, inst, select):
     n, cl = inst.shape[0], 4
-    col = orc.Colony(inst, ants=1, cand_len=cl, alpha=1, beta=2, seed=77)
+    col = orc.Colony(inst, ants=1, cand_len=cl, alpha=1, beta=2, seed=77, select=select)
     rng = np.random.default_rng(6)
     tau = rng.uniform(0.05, 1.0, size=(n, n)).astype(np.float32)
     col.set_pheromone(tau)
@@ -108,12 +110,13 @@ def test_fallback_frequencies_dense(orc, inst):
     chi2_ok(counts, {k: v / tot for k, v in w.items()}, DRAWS)
 
 
-def test_fallback_frequencies_candidate_mode(orc, inst):
+@pytest.mark.parametrize("select", ["wrs", "prwm"])
+def test_fallback_frequencies_candidate_mode(orc, inst, select):
     """Candidate-only trails: the fallback weight of an edge off the lists is
     tau_min^alpha * eta^beta."""
     n, cl = inst.shape[0], 4
     col = orc.Colony(inst, ants=1, cand_len=cl, alpha=2, beta=3, seed=5,
-                     pher_mode=orc.PHER_CANDIDATES)
+                     pher_mode=orc.PHER_CANDIDATES, select=select)
     col.prepare_choice()
     tmin, _ = col.limits()
     cur = 7
@@ -183,11 +186,12 @@ def exact_tour_probs(dist, tau, cl, alpha, beta):
     return probs
 
 
+@pytest.mark.parametrize("select", ["wrs", "prwm"])
 @pytest.mark.parametrize("n,cl", [(5, 2), (6, 3)])
-def test_whole_tour_distribution_brute_force(orc, n, cl):
+def test_whole_tour_distribution_brute_force(orc, n, cl, select):
     _, d = I.make_instance("uniform", n, seed=40 + n, side=100.0)
     ants = 150_000
-    col = orc.Colony(d, ants=ants, cand_len=cl, alpha=1, beta=2, seed=9)
+    col = orc.Colony(d, ants=ants, cand_len=cl, alpha=1, beta=2, seed=9, select=select)
     rng = np.random.default_rng(n)
     tau = rng.uniform(0.2, 1.0, size=(n, n)).astype(np.float32)
     col.set_pheromone(tau)
@@ -197,3 +201,50 @@ def test_whole_tour_distribution_brute_force(orc, n, cl):
     keys, cnt = np.unique(tours, axis=0, return_counts=True)
     counts = {tuple(int(x) for x in k): int(c) for k, c in zip(keys, cnt)}
     chi2_ok(counts, exact_tour_probs(d, tau, cl, 1, 2), ants)
+
+
+
+@pytest.mark.parametrize("select", ["wrs", "prwm"])
+def test_fallback_frequencies_many_nodes(orc, select):
+    """A fallback over about 290 unvisited nodes: the roulette wheel takes two
+    stages (64 chunks of 5, then the nodes of the winning chunk) and must
+    still pick node j with probability w_j / sum(w)."""
+    _, d = I.make_instance("uniform", 300, seed=9)
+    n, cl = 300, 4
+    col = orc.Colony(d, ants=1, cand_len=cl, alpha=1, beta=2, seed=31, select=select)
+    rng = np.random.default_rng(8)
+    tau = rng.uniform(0.05, 1.0, size=(n, n)).astype(np.float32)
+    col.set_pheromone(tau)
+    col.prepare_choice()
+    cur = 123
+    cands = ref_candidates(d, cl)[cur]
+    visited = np.zeros(n, np.uint8)
+    visited[cur] = 1
+    visited[cands] = 1
+    visited[rng.choice(n, 6, replace=False)] = 1
+    w = {j: float(tau[cur, j]) * (1.0 / d[cur, j]) ** 2 for j in range(n) if not visited[j]}
+    assert len(w) > 256
+    tot = sum(w.values())
+    counts, fbs = sample(col, cur, visited)
+    assert fbs == {True}
+    chi2_ok(counts, {k: v / tot for k, v in w.items()}, DRAWS)
+
+
+def test_prwm_single_unvisited_and_differs_from_wrs(orc, inst):
+    """The wheel over one unvisited candidate always returns it; over several,
+    its choices are its own (one draw per step), not those of WRS."""
+    n, cl = inst.shape[0], 6
+    col = orc.Colony(inst, ants=1, cand_len=cl, seed=3, select="prwm")
+    col.prepare_choice()
+    cur = 2
+    cands = ref_candidates(inst, cl)[cur]
+    visited = np.ones(n, np.uint8)
+    visited[cands[4]] = 0
+    for a in range(50):
+        assert col.select_next(cur, visited, 0, a, 1) == (int(cands[4]), False)
+    wrs = orc.Colony(inst, ants=1, cand_len=cl, seed=3)
+    wrs.prepare_choice()
+    visited = np.zeros(n, np.uint8)
+    visited[cur] = 1
+    picks = [(col.select_next(cur, visited, 0, a, 1), wrs.select_next(cur, visited, 0, a, 1)) for a in range(200)]
+    assert any(p != q for p, q in picks)
