@@ -53,6 +53,9 @@ enum { MMAS_PHER_DENSE = 0, MMAS_PHER_CANDIDATES = 1 };
 /* Whose tour deposits in the update (Sec. 2.1): the iteration best, or the
  * global best, which the paper allows instead. */
 enum { MMAS_DEPOSIT_ITERATION_BEST = 0, MMAS_DEPOSIT_GLOBAL_BEST = 1 };
+/* Node selection: weighted reservoir sampling (Alg. 4, the default) or the
+ * parallel roulette wheel of Sec. 4.2.1 (the paper's baseline). */
+enum { MMAS_SELECT_WRS = 0, MMAS_SELECT_PRWM = 1 };
 
 /* Run parameters. Sec. 5 lists the paper's settings (m = n ants, alpha = 1,
  * beta = 2, p_best = 0.01); Sec. 4.3 the candidate lists. */
@@ -162,6 +165,19 @@ mmas_status mmas_construct(mmas_ctx* ctx, uint32_t iteration);
  * ants x waves fit the GPU's SIMDs once. EINVAL for other values. */
 mmas_status mmas_set_launch(mmas_ctx* ctx, int32_t ants_per_block, int32_t table_rows, int32_t lanes_per_ant,
                             int32_t waves_per_ant);
+
+/* Node selection of the construction. MMAS_SELECT_PRWM: the parallel
+ * roulette wheel of Sec. 4.2.1 with p = 64 (one wave per ant): one draw per
+ * step (slot 0); over the unvisited candidates by rank, or over every
+ * unvisited city in index order; 64 chunks a stage, chunk sums left to
+ * right, their prefix sums in a wave scan's order (log steps within rows of
+ * 16, then the earlier rows' totals), target u times the total, the first
+ * chunk whose prefix exceeds the target (else the last with a positive sum),
+ * repeated inside it with the target less the prefix before it; every weight
+ * 0 gives the lowest entry. Bitmask tabu only (EUNSUPPORTED otherwise), the
+ * launch options do not apply, and a batch's constructions ignore it.
+ * MMAS_SELECT_WRS (default): Alg. 4. */
+mmas_status mmas_set_selection(mmas_ctx* ctx, int32_t select);
 
 /* 2-opt on every ant's tour with ls_nn-nearest-neighbour lists and don't-look
  * bits (Sec. 5.7), as a sequential first-improvement search (cities in index

@@ -482,6 +482,7 @@ static int prwm_pick(const float* w, int m, float u) {
             if (P[l] > target && s[l] > 0.0f) win = l;
         for (int l = 63; l >= 0 && win < 0; --l)
             if (s[l] > 0.0f) win = l;
+        if (win < 0) win = 0;
         if (win > 0) target = target - P[win - 1];
         lo += win * c;
         if (c == 1) return lo;
@@ -502,21 +503,23 @@ static int select_prwm(const orc_colony* c, int cur, const uint8_t* visited, uin
     for (int r = 0; r < cl; ++r) {
         int v = c->cand[(size_t)cur * cl + r];
         w[r] = visited[v] ? 0.0f : c->chc[(size_t)cur * cl + r];
-        any |= !visited[v];
+        any |= w[r] > 0.0f;
     }
     *fallback = 0;
     if (any) return c->cand[(size_t)cur * cl + prwm_pick(w, cl, u)];
     *fallback = 1;
     int* list = (int*)malloc(sizeof(int) * (size_t)n);
     float* wl = (float*)malloc(sizeof(float) * (size_t)n);
-    int L = 0;
+    int L = 0, pos = 0;
     for (int v = 0; v < n; ++v)
         if (!visited[v]) {
             list[L] = v;
             wl[L] = fallback_weight(c, cur, v);
+            pos |= wl[L] > 0.0f;
             ++L;
         }
-    int v = L > 0 ? list[prwm_pick(wl, L, u)] : -1;
+    /* (every weight 0: the lowest unvisited node, as WRS's equal keys give) */
+    int v = L == 0 ? -1 : pos ? list[prwm_pick(wl, L, u)] : list[0];
     free(list);
     free(wl);
     return v;

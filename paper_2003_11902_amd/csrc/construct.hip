@@ -1031,6 +1031,180 @@ int batch_construct_grid(int tabu, int pher, int ants_per_block, int lanes_per_a
 
 namespace {
 
+// ---- the parallel roulette wheel (Sec. 4.2.1), the paper's baseline ---------
+
+// Inclusive prefix sum of FP32 values over the wave: a log-step scan within
+// each row of 16 (lanes below the shift add 0), then every row adds the
+// totals of the rows before it, in a fixed order.
+__device__ __forceinline__ float wave_scan_f32(float x, int lane) {
+    x = x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x111, 0xF, 0xF, false));
+    x = x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x112, 0xF, 0xF, false));
+    x = x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x114, 0xF, 0xF, false));
+    x = x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x118, 0xF, 0xF, false));
+    const float t0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 15));
+    const float t1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 31));
+    const float t2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 47));
+    const int row = lane >> 4;
+    float add = 0.0f;
+    if (row >= 1) add = t0;
+    if (row >= 2) add = add + t1;
+    if (row >= 3) add = add + t2;
+    return x + add;
+}
+
+// The wheel over entries 0 .. m-1 of `list` with weights wt(list[i]): 64
+// chunks of ceil(len/64) a stage (chunk sums left to right), their prefix
+// sums, target u times the total, the first chunk whose prefix exceeds it
+// (the last with a positive sum if rounding leaves none), the target less the
+// prefix before it, and again inside that chunk until a chunk is one entry.
+// Returns the entry; 0 if every weight is 0.
+template <class W>
+__device__ int prwm_list(const uint16_t* list, int m, const W& wt, float u, int lane) {
+    int lo = 0, len = m;
+    float target = 0.0f;
+    bool first = true;
+    for (;;) {
+        const int c = (len + 63) >> 6;
+        float a = 0.0f;
+        const int q1 = (lane + 1) * c < len ? (lane + 1) * c : len;
+        for (int q = lane * c; q < q1; ++q) a = a + wt((uint32_t)list[lo + q]);
+        const float P = wave_scan_f32(a, lane);
+        if (first) {
+            const uint64_t pos = __ballot(a > 0.0f);
+            if (pos == 0ull) return 0;
+            target = u * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(P), 63));
+            first = false;
+        }
+        const uint64_t over = __ballot((P > target) & (a > 0.0f));
+        const uint64_t pos = __ballot(a > 0.0f);
+        const int win = over ? (int)__builtin_ctzll(over) : pos ? 63 - (int)__builtin_clzll(pos) : 0;
+        if (win > 0) target = target - __int_as_float(__builtin_amdgcn_readlane(__float_as_int(P), win - 1));
+        lo += win * c;
+        if (c == 1) return lo;
+        len = len - win * c < c ? len - win * c : c;
+    }
+}
+
+// One ant per wave, bitmask tabu and the full list of unvisited cities in
+// LDS (the wheel's chunks follow the ascending city order), rows read from
+// global memory. One draw per step (slot 0).
+template <int kPher>
+__global__ __launch_bounds__(256) void k_construct_prwm(Views vw, Shape s, uint32_t it, int ants_per_block,
+                                                        int per_ant) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int ant = blockIdx.x * ants_per_block + wave;
+    if (ant >= s.ants) return;
+    const int n = s.n, cl = s.cl;
+    uint8_t* region = smem + (size_t)wave * per_ant;
+    BitmaskTabu tabu;
+    tabu.init(region, n, lane);
+    uint16_t* ulist = reinterpret_cast<uint16_t*>(region + align16(4 * ((n + 31) / 32)));
+    float tmin_a = 0.0f;
+    if (kPher == MMAS_PHER_CANDIDATES) tmin_a = powi(vw.state->tau_min, s.alpha);
+    const uint32_t x0 = draw_block(s.seed, it, (uint32_t)ant, 0u, 0u).w[0];
+    const uint32_t start = (uint32_t)(((uint64_t)x0 * (uint64_t)n) >> 32);
+    tabu.mark(start, lane);
+    uint16_t* tour_out = vw.tours + (size_t)ant * n;
+    const int32_t* dist = vw.dist;
+    uint32_t tbuf = start, prev_last = 0, cur = start;
+    int64_t len = 0, fb_steps = 0, fb_nodes = 0;
+    for (int k = 1; k < n; ++k) {
+        const float u = u01(draw_block(s.seed, it, (uint32_t)ant, (uint32_t)k, 0u).w[0]);
+        uint32_t next = kNone;
+        if (cl > 0) {
+            const int e = (int)cur * cl + (lane < cl ? lane : cl - 1);
+            const uint32_t node = vw.cand[e];
+            const float w = vw.chc[e];
+            const float a = (lane < cl) & !tabu.visited(node) ? w : 0.0f;
+            const uint64_t pos = __ballot(a > 0.0f);
+            if (pos) {
+                const float P = wave_scan_f32(a, lane);
+                const float target = u * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(P), 63));
+                const uint64_t over = __ballot((P > target) & (a > 0.0f));
+                const int win = over ? (int)__builtin_ctzll(over) : 63 - (int)__builtin_clzll(pos);
+                next = (uint32_t)__builtin_amdgcn_readlane((int)node, win);
+            }
+        }
+        if (next == kNone) {
+            fb_steps += 1;
+            fb_nodes += n - k;
+            // every unvisited city, ascending (one pass: the list has room for n)
+            const int words = (n + 31) >> 5;
+            int L = 0;
+            for (int w0 = 0; w0 < words; w0 += kWave) {
+                const int wi = w0 + lane;
+                uint32_t fr = 0u;
+                if (wi < words) {
+                    fr = ~tabu.bits[wi];
+                    if (wi == words - 1 && (n & 31)) fr &= (1u << (n & 31)) - 1u;
+                }
+                const int cnt = __popc(fr);
+                const int incl = wave_incl_scan(cnt, lane);
+                int p = L + incl - cnt;
+                while (fr) {
+                    const int b = __ffs(fr) - 1;
+                    fr &= fr - 1u;
+                    ulist[p++] = (uint16_t)(wi * 32 + b);
+                }
+                L += __builtin_amdgcn_readlane(incl, 63);
+            }
+            int pick;
+            if constexpr (kPher == MMAS_PHER_DENSE) {
+                const DenseWeight wt{vw.choice + (size_t)cur * n};
+                pick = prwm_list(ulist, L, wt, u, lane);
+            } else {
+                const CandWeight wt{dist + (size_t)cur * n, tmin_a, s.beta};
+                pick = prwm_list(ulist, L, wt, u, lane);
+            }
+            next = L > 0 ? (uint32_t)ulist[pick] : kNone;
+        }
+        next = (uint32_t)__builtin_amdgcn_readfirstlane((int)next);
+        if (next >= (uint32_t)n) {
+            if (lane == 0) atomicOr(&vw.state->flags, 8u);
+            return;
+        }
+        tabu.mark(next, lane);
+        const int slot = k & 63;
+        if (lane == slot) tbuf = next;
+        cur = next;
+        if (slot == 63 || k == n - 1) {
+            const int k0 = k - slot;
+            const uint32_t prev = __shfl_up(tbuf, 1);
+            if (lane <= slot) {
+                tour_out[k0 + lane] = (uint16_t)tbuf;
+                const uint32_t from = lane == 0 ? prev_last : prev;
+                if (k0 + lane > 0) len += dist[(size_t)from * n + tbuf];
+            }
+            prev_last = (uint32_t)__builtin_amdgcn_readlane((int)tbuf, slot);
+        }
+    }
+    if (lane == 0) len += dist[(size_t)cur * n + start];
+    len = wave_sum_i64(len);
+    if (lane == 0) {
+        vw.lengths[ant] = len;
+        vw.fallback[ant] = fb_steps;
+        vw.fallback[s.ants + ant] = fb_nodes;
+    }
+}
+
+template <int kPher>
+hipError_t launch_prwm(const Views& v, const Shape& s, uint32_t it, hipStream_t st) {
+    const int per_ant = align16(4 * ((s.n + 31) / 32)) + align16(2 * s.n);
+    const int budget = max_lds_per_block();
+    int apb = 4;
+    while (apb > 1 && apb * per_ant > budget) --apb;
+    if (apb * per_ant > budget) return hipErrorInvalidValue;
+    const size_t bytes = (size_t)apb * per_ant;
+    auto kern = k_construct_prwm<kPher>;
+    if (bytes > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    kern<<<(s.ants + apb - 1) / apb, 64 * apb, bytes, st>>>(v, s, it, apb, per_ant);
+    return hipGetLastError();
+}
+
 // One wave marks marks[0 .. count) in a fresh tabu of n cities, in order, then
 // writes visited[v] for every city, the tabu's cells (bitmask: its 32-bit
 // words as pairs of 16-bit halves, low first; compact: entries[0 .. n); list:
@@ -1086,6 +1260,9 @@ hipError_t launch_eval_tabu(int tabu, int n, const int32_t* marks, int count, ui
 }
 
 hipError_t launch_construct(const Views& v, const Shape& s, uint32_t it, hipStream_t st) {
+    if (s.select == MMAS_SELECT_PRWM)
+        return s.pher == MMAS_PHER_DENSE ? launch_prwm<MMAS_PHER_DENSE>(v, s, it, st)
+                                         : launch_prwm<MMAS_PHER_CANDIDATES>(v, s, it, st);
     if (s.tabu == MMAS_TABU_BITMASK) {
         return s.pher == MMAS_PHER_DENSE ? launch_tp<MMAS_TABU_BITMASK, MMAS_PHER_DENSE>(v, s, it, st)
                                          : launch_tp<MMAS_TABU_BITMASK, MMAS_PHER_CANDIDATES>(v, s, it, st);

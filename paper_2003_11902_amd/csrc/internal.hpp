@@ -40,6 +40,7 @@ struct Shape {
     int pher;    // MMAS_PHER_*
     int tabu;    // MMAS_TABU_*
     int deposit; // MMAS_DEPOSIT_*
+    int select;  // MMAS_SELECT_* (node selection)
     float rho;
     double pdec; // p_best^(1/n)
     uint64_t seed;

@@ -255,6 +255,13 @@ mmas_status mmas_set_launch(mmas_ctx* c, int32_t ants_per_block, int32_t table_r
     return MMAS_OK;
 }
 
+mmas_status mmas_set_selection(mmas_ctx* c, int32_t select) {
+    if (!c || (select != MMAS_SELECT_WRS && select != MMAS_SELECT_PRWM)) return MMAS_EINVAL;
+    if (select == MMAS_SELECT_PRWM && c->s.tabu != MMAS_TABU_BITMASK) return MMAS_EUNSUPPORTED;
+    c->s.select = select;
+    return MMAS_OK;
+}
+
 mmas_status mmas_set_two_opt_launch(mmas_ctx* c, int32_t waves_per_ant) {
     if (!c) return MMAS_EINVAL;
     if (waves_per_ant != 0 && waves_per_ant != 1 && waves_per_ant != 2 && waves_per_ant != 4 && waves_per_ant != 8 &&

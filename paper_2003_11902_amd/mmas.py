@@ -46,13 +46,14 @@ MMAS_BUF_LSNN = 12
 
 TABU = {"bitmask": MMAS_TABU_BITMASK, "compact": MMAS_TABU_COMPACT, "list": MMAS_TABU_LIST}
 DEPOSIT = {"iteration": 0, "global": 1}
+SELECT = {"wrs": 0, "prwm": 1}
 PHER = {"dense": MMAS_PHER_DENSE, "candidates": MMAS_PHER_CANDIDATES}
 
 EXPORTED = (
     "mmas_workspace_bytes", "mmas_create", "mmas_prepare_choice_info", "mmas_construct",
     "mmas_two_opt", "mmas_update_pheromone", "mmas_best", "mmas_buffer", "mmas_read",
     "mmas_set_pheromone", "mmas_synchronize", "mmas_destroy", "mmas_status_str",
-    "mmas_eval_log", "mmas_eval_draws", "mmas_eval_tabu", "mmas_set_launch",
+    "mmas_eval_log", "mmas_eval_draws", "mmas_eval_tabu", "mmas_set_selection", "mmas_set_launch",
     "mmas_batch_workspace_bytes", "mmas_batch_create", "mmas_batch_set_launch", "mmas_batch_tune",
     "mmas_batch_capture", "mmas_batch_step", "mmas_batch_iteration", "mmas_batch_context",
     "mmas_batch_destroy", "mmas_mlp_param_count", "mmas_mlp_packed_count", "mmas_mlp_features",
@@ -127,6 +128,8 @@ def _load():
     L.mmas_eval_draws.restype = C.c_int
     L.mmas_eval_tabu.argtypes = [C.c_int32, C.c_int32, p, C.c_int32, p, p, p, p]
     L.mmas_eval_tabu.restype = C.c_int
+    L.mmas_set_selection.argtypes = [p, C.c_int32]
+    L.mmas_set_selection.restype = C.c_int
     L.mmas_batch_workspace_bytes.argtypes = [C.c_int32, p, C.POINTER(C.c_size_t)]
     L.mmas_batch_workspace_bytes.restype = C.c_int
     L.mmas_batch_create.argtypes = [C.c_int32, p, p, p, C.c_size_t, p, C.POINTER(p)]
@@ -302,6 +305,9 @@ class Colony:
 
     def set_two_opt_launch(self, waves_per_ant=0):
         _check(lib.mmas_set_two_opt_launch(self._ctx, waves_per_ant), "mmas_set_two_opt_launch")
+
+    def set_selection(self, select="wrs"):
+        _check(lib.mmas_set_selection(self._ctx, SELECT.get(select, select)), "mmas_set_selection")
 
     def update_pheromone(self):
         _check(lib.mmas_update_pheromone(self._ctx), "mmas_update_pheromone")
