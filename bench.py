@@ -170,6 +170,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="clustered1002")
     ap.add_argument("--tabu", default="bitmask", choices=["bitmask", "compact", "list"])
+    ap.add_argument("--select", default="wrs", choices=["wrs", "prwm"],
+                    help="node selection: weighted reservoir sampling or the parallel roulette wheel")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--ants", type=int, default=0, help="override the workload's ant count")
     ap.add_argument("--ants-per-block", type=int, default=0)
@@ -223,6 +225,8 @@ def main():
     col = M.Colony(dist, w["ants"], cand_len=w["cand_len"], alpha=w["alpha"], beta=w["beta"],
                    rho=w["rho"], seed=args.seed, tabu=args.tabu, pher=w["pher"], ls_nn=w["ls_nn"])
     col.set_launch(args.ants_per_block, args.table_rows, args.lanes_per_ant, args.waves_per_ant)
+    if args.select != "wrs":
+        col.set_selection(args.select)
     stream = col.stream
 
     def step(it):
@@ -277,15 +281,16 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "ants": w["ants"], "cand_len": w["cand_len"],
-                   "alpha": w["alpha"], "beta": w["beta"], "rho": w["rho"], "tabu": args.tabu,
+                   "alpha": w["alpha"], "beta": w["beta"], "rho": w["rho"], "tabu": args.tabu, "select": args.select,
                    "pheromone": w["pher"], "instance": f"{w['kind']} seed {w['seed']}",
                    "ants_per_block": args.ants_per_block or 4, "table_rows": args.table_rows,
                    "lanes_per_ant": args.lanes_per_ant, "waves_per_ant": args.waves_per_ant or "auto"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": (measured_traffic(args.workload)
-                                 if args.tabu == "bitmask" and args.cand_len is None and not args.ants else None),
-                     "kernel": "k_construct", "kernel_ms": cons_ms,
+                                 if args.tabu == "bitmask" and args.select == "wrs" and args.cand_len is None
+                                 and not args.ants else None),
+                     "kernel": "k_construct" if args.select == "wrs" else "k_construct_prwm", "kernel_ms": cons_ms,
                      "construct_only_tours_per_s": w["ants"] / (cons_ms * 1e-3),
                      "bytes_per_launch": nbytes},
     }
