@@ -325,6 +325,7 @@ struct orc_colony {
     int has_gb;
     int deposit;      /* ORC_DEPOSIT_ITERATION_BEST or ORC_DEPOSIT_GLOBAL_BEST */
     int select;       /* ORC_SELECT_WRS or ORC_SELECT_PRWM */
+    int directed;     /* ORC_PROBLEM_ATSP: edges (i,j) are directed */
     int64_t gb_len;
     uint16_t* gb_tour;
     float tmin, tmax;
@@ -609,7 +610,8 @@ void orc_two_opt(orc_colony* c, int nthreads) {
  * 1/C_ib on both directions of the iteration best's edges (or, with the
  * global-best deposit that Sec. 2.1 allows, 1/C_gb on the global best's,
  * the global best being updated first); every stored trail clamped to
- * tau_max. */
+ * tau_max. On an asymmetric instance the tour's edge (i,j) is its arc from
+ * i to the successor j, and only tau_ij receives the deposit. */
 void orc_update(orc_colony* c) {
     int n = c->n, cl = c->cl;
     int ib = 0;
@@ -642,7 +644,7 @@ void orc_update(orc_colony* c) {
                 float* t = &c->tau[(size_t)i * n + j];
                 float v = keep * *t;
                 if (v < tmin) v = tmin;
-                if (j == succ[i] || j == pred[i]) v = v + delta;
+                if (j == succ[i] || (!c->directed && j == pred[i])) v = v + delta;
                 if (v > tmax) v = tmax;
                 *t = v;
             }
@@ -653,7 +655,7 @@ void orc_update(orc_colony* c) {
                 float* t = &c->tau[(size_t)i * cl + r];
                 float v = keep * *t;
                 if (v < tmin) v = tmin;
-                if (j == succ[i] || j == pred[i]) v = v + delta;
+                if (j == succ[i] || (!c->directed && j == pred[i])) v = v + delta;
                 if (v > tmax) v = tmax;
                 *t = v;
             }
@@ -673,6 +675,12 @@ void orc_iterate(orc_colony* c, uint32_t it, int nthreads) {
 int orc_set_select(orc_colony* c, int mode) {
     if (mode != ORC_SELECT_WRS && mode != ORC_SELECT_PRWM) return -1;
     c->select = mode;
+    return 0;
+}
+int orc_set_problem(orc_colony* c, int mode) {
+    if (mode != ORC_PROBLEM_TSP && mode != ORC_PROBLEM_ATSP) return -1;
+    if (mode == ORC_PROBLEM_ATSP && c->ls_nn > 0) return -1;
+    c->directed = mode == ORC_PROBLEM_ATSP;
     return 0;
 }
 int orc_set_deposit(orc_colony* c, int mode) {

@@ -92,6 +92,13 @@ int orc_set_deposit(orc_colony* c, int mode);
 enum { ORC_SELECT_WRS = 0, ORC_SELECT_PRWM = 1 };
 int orc_set_select(orc_colony* c, int mode);
 
+/* The problem (Sec. 2.1): the symmetric TSP (default), or the asymmetric TSP,
+ * where d_ij and d_ji may differ, an edge (i,j) is directed and the deposit
+ * reaches (i,j) only. Returns -1 for another mode, and for the ATSP when 2-opt
+ * is on (reversing a path changes an asymmetric tour's length). */
+enum { ORC_PROBLEM_TSP = 0, ORC_PROBLEM_ATSP = 1 };
+int orc_set_problem(orc_colony* c, int mode);
+
 /* The per-iteration calls, in Alg. 1 order. */
 void orc_prepare_choice(orc_colony* c);              /* choice_info = tau^alpha * eta^beta */
 void orc_construct(orc_colony* c, uint32_t it, int nthreads); /* every ant builds a tour */

@@ -48,6 +48,8 @@ def lib():
         L.orc_set_deposit.restype = C.c_int
         L.orc_set_select.argtypes = [p, C.c_int]
         L.orc_set_select.restype = C.c_int
+        L.orc_set_problem.argtypes = [p, C.c_int]
+        L.orc_set_problem.restype = C.c_int
         L.orc_prepare_choice.argtypes = [p]
         L.orc_construct.argtypes = [p, C.c_uint32, C.c_int]
         L.orc_two_opt.argtypes = [p, C.c_int]
@@ -191,7 +193,7 @@ class Colony:
     """One oracle colony (Alg. 1 state for one instance)."""
 
     def __init__(self, dist, ants, cand_len=32, alpha=1, beta=2, rho=0.02, p_best=0.01,
-                 seed=1, pher_mode=PHER_DENSE, ls_nn=0, deposit=0, select="wrs"):
+                 seed=1, pher_mode=PHER_DENSE, ls_nn=0, deposit=0, select="wrs", problem="tsp"):
         self.dist = np.ascontiguousarray(dist, dtype=np.int32)
         self.n = int(self.dist.shape[0])
         self.ants = int(ants)
@@ -205,6 +207,8 @@ class Colony:
             raise ValueError("unknown deposit mode")
         if lib().orc_set_select(self._h, {"wrs": 0, "prwm": 1}.get(select, select)) != 0:
             raise ValueError("unknown selection")
+        if lib().orc_set_problem(self._h, {"tsp": 0, "atsp": 1}.get(problem, problem)) != 0:
+            raise ValueError("unknown problem, or 2-opt on an asymmetric instance")
         self.cl = int(lib().orc_cl(self._h))
 
     def close(self):

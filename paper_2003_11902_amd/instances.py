@@ -9,6 +9,11 @@ not reproduced here; these generators stand in for them with the same sizes and
 the two spatial structures that matter for candidate lists: cities spread
 uniformly over a square, and cities gathered in Gaussian clusters.
 
+The asymmetric instances (the ATSP of Sec. 2.1) start from such a matrix and
+add to each ordered pair (i, j) its own surcharge, floor(f u_ij d_ij) with
+u_ij uniform in [0, 1): a one-way detour, so d_ij and d_ji differ while staying
+positive.
+
 Distances follow the usual Euclidean convention for integer instances,
 d = floor(sqrt(dx^2 + dy^2) + 0.5), computed in float64. The problem statement
 (Sec. 2.1) requires positive distances between distinct cities, so any city whose
@@ -23,6 +28,7 @@ __all__ = [
     "clustered_coords",
     "distance_matrix",
     "make_instance",
+    "asymmetric",
     "WORKLOADS",
 ]
 
@@ -92,6 +98,21 @@ def make_instance(kind: str, n: int, seed: int, side: float = 10000.0,
     return xy, distance_matrix(xy)
 
 
+def asymmetric(dist: np.ndarray, frac: float, seed: int) -> np.ndarray:
+    """d_ij + floor(frac * u_ij * d_ij) for i != j, u_ij uniform in [0, 1) from
+    numpy PCG64 stream `seed` drawn row by row; the diagonal stays 0."""
+    d = np.asarray(dist, dtype=np.int32)
+    n = d.shape[0]
+    rng = np.random.default_rng(seed)
+    out = np.empty_like(d)
+    for i in range(n):
+        u = rng.random(n)
+        row = d[i].astype(np.int64)
+        out[i] = (row + np.floor(frac * u * row)).astype(np.int32)
+    out[np.arange(n), np.arange(n)] = 0
+    return out
+
+
 # The synthetic workloads, sized like the paper's instances (d198, pr1002,
 # d18512 and fl3795 by size only). Each entry is the recipe; the run parameters
 # (ants, candidate list, rho, iterations, tabu) travel with it.
@@ -106,6 +127,10 @@ WORKLOADS = {
                               pher="candidates"),
     "uniform3795": dict(kind="uniform", n=3795, seed=5, side=1e4, ants=3795, cand_len=32,
                         alpha=1, beta=2, rho=0.02, iterations=500, ls_nn=0, pher="dense"),
+    # the clustered 1002-city instance with one-way surcharges up to 50 %
+    "clustered1002_atsp": dict(kind="clustered", n=1002, seed=2, side=1e4, clusters=20, sigma=300.0,
+                               asym=0.5, asym_seed=7, problem="atsp", ants=1002, cand_len=32,
+                               alpha=1, beta=2, rho=0.02, iterations=500, ls_nn=0, pher="dense"),
 }
 
 
@@ -116,6 +141,9 @@ def workload_instance(name: str):
     if w["kind"] == "clustered":
         kw.update(clusters=w["clusters"], sigma=w["sigma"])
     xy, dist = make_instance(**kw)
+    if w.get("asym"):
+        dist = asymmetric(dist, w["asym"], w["asym_seed"])
+    w.setdefault("problem", "tsp")
     return xy, dist, w
 
 

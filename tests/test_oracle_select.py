@@ -186,12 +186,17 @@ def exact_tour_probs(dist, tau, cl, alpha, beta):
     return probs
 
 
+@pytest.mark.parametrize("asym", [False, True])
 @pytest.mark.parametrize("select", ["wrs", "prwm"])
 @pytest.mark.parametrize("n,cl", [(5, 2), (6, 3)])
-def test_whole_tour_distribution_brute_force(orc, n, cl, select):
+def test_whole_tour_distribution_brute_force(orc, n, cl, select, asym):
+    """With an asymmetric matrix, the step out of c weighs d[c, j] (row c)."""
     _, d = I.make_instance("uniform", n, seed=40 + n, side=100.0)
+    if asym:
+        d = I.asymmetric(d, 1.0, seed=n)
     ants = 150_000
-    col = orc.Colony(d, ants=ants, cand_len=cl, alpha=1, beta=2, seed=9, select=select)
+    col = orc.Colony(d, ants=ants, cand_len=cl, alpha=1, beta=2, seed=9, select=select,
+                     problem="atsp" if asym else "tsp")
     rng = np.random.default_rng(n)
     tau = rng.uniform(0.2, 1.0, size=(n, n)).astype(np.float32)
     col.set_pheromone(tau)
