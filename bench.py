@@ -69,7 +69,7 @@ def cpu_baseline(dist, w, seed, budget_s):
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     threads = max(1, min(threads, 16))
     o = O.Colony(dist, w["ants"], cand_len=w["cand_len"], alpha=w["alpha"], beta=w["beta"],
-                 rho=w["rho"], seed=seed)
+                 rho=w["rho"], seed=seed, problem=w.get("problem", "tsp"))
     t0 = time.perf_counter()
     it = 0
     while True:
@@ -80,7 +80,7 @@ def cpu_baseline(dist, w, seed, budget_s):
             break
     # and one thread, as the paper's CPU runs: a few iterations of a fresh colony
     o1 = O.Colony(dist, w["ants"], cand_len=w["cand_len"], alpha=w["alpha"], beta=w["beta"],
-                  rho=w["rho"], seed=seed)
+                  rho=w["rho"], seed=seed, problem=w.get("problem", "tsp"))
     t1 = time.perf_counter()
     it1 = 0
     while True:
@@ -110,7 +110,7 @@ def run_batched(args):
         _, d0, w = I.workload_instance(args.batch_of)
         dists = [d0] * args.batch_count
         params = [M.make_params(w["n"], w["ants"], cand_len=w["cand_len"], alpha=w["alpha"], beta=w["beta"],
-                                rho=w["rho"], seed=1 + k, tabu=args.tabu, pher=w["pher"])
+                                rho=w["rho"], seed=1 + k, tabu=args.tabu, pher=w["pher"], problem=w["problem"])
                   for k in range(args.batch_count)]
         workload = f"{args.batch_of} x {args.batch_count} colonies"
     else:
@@ -223,7 +223,8 @@ def main():
         w["cand_len"] = args.cand_len
     n = w["n"]
     col = M.Colony(dist, w["ants"], cand_len=w["cand_len"], alpha=w["alpha"], beta=w["beta"],
-                   rho=w["rho"], seed=args.seed, tabu=args.tabu, pher=w["pher"], ls_nn=w["ls_nn"])
+                   rho=w["rho"], seed=args.seed, tabu=args.tabu, pher=w["pher"], ls_nn=w["ls_nn"],
+                   problem=w["problem"])
     col.set_launch(args.ants_per_block, args.table_rows, args.lanes_per_ant, args.waves_per_ant)
     if args.select != "wrs":
         col.set_selection(args.select)
@@ -282,7 +283,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "ants": w["ants"], "cand_len": w["cand_len"],
                    "alpha": w["alpha"], "beta": w["beta"], "rho": w["rho"], "tabu": args.tabu, "select": args.select,
-                   "pheromone": w["pher"], "instance": f"{w['kind']} seed {w['seed']}",
+                   "pheromone": w["pher"], "problem": w["problem"],
+                   "instance": f"{w['kind']} seed {w['seed']}"
+                               + (f", one-way surcharges up to {w['asym']:.0%}" if w.get("asym") else ""),
                    "ants_per_block": args.ants_per_block or 4, "table_rows": args.table_rows,
                    "lanes_per_ant": args.lanes_per_ant, "waves_per_ant": args.waves_per_ant or "auto"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -56,6 +56,11 @@ enum { MMAS_DEPOSIT_ITERATION_BEST = 0, MMAS_DEPOSIT_GLOBAL_BEST = 1 };
 /* Node selection: weighted reservoir sampling (Alg. 4, the default) or the
  * parallel roulette wheel of Sec. 4.2.1 (the paper's baseline). */
 enum { MMAS_SELECT_WRS = 0, MMAS_SELECT_PRWM = 1 };
+/* The problem (Sec. 2.1): the symmetric TSP, or the asymmetric TSP, whose
+ * d_ij may differ from d_ji. An ATSP edge (i,j) is directed: its trail is
+ * tau_ij alone, a tour's length sums d along its direction, and the deposit
+ * goes to (i,j) only. */
+enum { MMAS_PROBLEM_TSP = 0, MMAS_PROBLEM_ATSP = 1 };
 
 /* Run parameters. Sec. 5 lists the paper's settings (m = n ants, alpha = 1,
  * beta = 2, p_best = 0.01); Sec. 4.3 the candidate lists. */
@@ -77,6 +82,9 @@ typedef struct mmas_params {
     int32_t ls_nn;     /* 2-opt neighbour-list length 0..32 (the paper uses 32),
                           0 = no local search */
     int32_t deposit;   /* MMAS_DEPOSIT_ITERATION_BEST (0) or MMAS_DEPOSIT_GLOBAL_BEST */
+    int32_t problem;   /* MMAS_PROBLEM_TSP (0) or MMAS_PROBLEM_ATSP; ATSP needs
+                          ls_nn == 0 (2-opt reverses paths, which changes the
+                          length of an asymmetric tour) */
 } mmas_params;
 
 typedef struct mmas_ctx mmas_ctx;
@@ -91,7 +99,7 @@ typedef struct mmas_device_state {
     int64_t ib_len;    /* its length, -1 before */
     int64_t gb_len;    /* global-best length, -1 while there is none */
     int64_t nn_len;    /* nearest-neighbour tour length (set-up) */
-    uint32_t flags;    /* 1/2/4: distance matrix asymmetric / non-zero diagonal /
+    uint32_t flags;    /* 1/2/4: distance matrix asymmetric (TSP only) / non-zero diagonal /
                           non-positive off the diagonal (set-up); 8: a
                           construction step found no city (never expected);
                           16: a 2-opt search hit its round limit (never
@@ -122,8 +130,9 @@ size_t mmas_workspace_bytes(const mmas_params* p);
 
 /* Set-up (Alg. 1 before its loop). Copies `dist_host` (n*n int32, row-major,
  * host memory; the caller may free it on return) into the workspace, checks it
- * (symmetric, zero diagonal, positive elsewhere: Sec. 2.1 requires positive
- * distances and the deposit of Sec. 2.1 treats (i,j) and (j,i) as one edge),
+ * (zero diagonal, positive elsewhere: Sec. 2.1 requires positive distances;
+ * for MMAS_PROBLEM_TSP also symmetric, since its deposit treats (i,j) and
+ * (j,i) as one edge),
  * and then on the GPU: eta = 1/d and eta^beta (Sec. 2.1), the candidate lists of
  * the cl nearest cities by (distance, index) (Sec. 4.3), the 2-opt neighbour
  * lists, the nearest-neighbour tour from city 0 (ties to the lowest index),
@@ -196,8 +205,9 @@ mmas_status mmas_set_two_opt_launch(mmas_ctx* ctx, int32_t waves_per_ant);
  * lowest ant on ties); if it beats the global best (or there is none) it
  * becomes the global best and the limits are recomputed from its length;
  * then tau <- max(fl((1-rho) tau), tau_min), plus 1/C_ib on both directions
- * of the iteration best's edges (with MMAS_DEPOSIT_GLOBAL_BEST: 1/C_gb on
- * the global best's), then min(., tau_max) on every stored trail;
+ * of the iteration best's edges (MMAS_PROBLEM_ATSP: on (i, succ(i)) only;
+ * with MMAS_DEPOSIT_GLOBAL_BEST: 1/C_gb on the global best's), then
+ * min(., tau_max) on every stored trail;
  * choice_info is refreshed in the same pass. ESTATE before a construct. */
 mmas_status mmas_update_pheromone(mmas_ctx* ctx);
 
@@ -339,7 +349,8 @@ mmas_status mmas_mlp_labels(const uint16_t* tours_dev, int32_t tours, int32_t n,
  * n*16 floats by edge 16 i + r, knn_dev: n*16); every other edge of i takes
  * the multiplier of i's lowest score, fl(2 sigmoid(min_r s_ir)), so all-zero
  * scores give the plain eta = 1/d; sigmoid uses the library's FP32 exp.
- * Marks choice_info stale. n >= 17. */
+ * Marks choice_info stale. n >= 17. EUNSUPPORTED for MMAS_PROBLEM_ATSP (the
+ * features and labels treat edges as undirected). */
 mmas_status mmas_set_learned_heuristic(mmas_ctx* ctx, const uint16_t* knn_dev, const float* score_dev);
 
 /* Diagnostics, for checking the device arithmetic against an independent

@@ -41,6 +41,7 @@ struct Shape {
     int tabu;    // MMAS_TABU_*
     int deposit; // MMAS_DEPOSIT_*
     int select;  // MMAS_SELECT_* (node selection)
+    int directed; // 1 for MMAS_PROBLEM_ATSP: deposit on (i, succ(i)) only
     float rho;
     double pdec; // p_best^(1/n)
     uint64_t seed;

@@ -3,12 +3,15 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
 
 #include "internal.hpp"
+
+static_assert(sizeof(mmas_params) == 64 && offsetof(mmas_params, problem) == 56, "mmas_params layout");
 
 using mmas::Shape;
 using mmas::Views;
@@ -47,6 +50,8 @@ bool params_ok(const mmas_params* p) {
     if (p->pher_mode == MMAS_PHER_CANDIDATES && cl == 0) return false;
     if (p->ls_nn < 0 || p->ls_nn > 32 || p->ls_nn > p->n - 1) return false;
     if (p->deposit != MMAS_DEPOSIT_ITERATION_BEST && p->deposit != MMAS_DEPOSIT_GLOBAL_BEST) return false;
+    if (p->problem != MMAS_PROBLEM_TSP && p->problem != MMAS_PROBLEM_ATSP) return false;
+    if (p->problem == MMAS_PROBLEM_ATSP && p->ls_nn != 0) return false;
     return true;
 }
 
@@ -61,6 +66,7 @@ Shape shape_of(const mmas_params* p) {
     s.pher = p->pher_mode;
     s.tabu = p->tabu;
     s.deposit = p->deposit;
+    s.directed = p->problem == MMAS_PROBLEM_ATSP ? 1 : 0;
     s.rho = p->rho;
     s.pdec = std::pow(p->p_best, 1.0 / (double)p->n);
     s.seed = p->seed;
@@ -333,6 +339,7 @@ mmas_status mmas_set_pheromone(mmas_ctx* c, const float* host_src) {
 
 mmas_status mmas_set_learned_heuristic(mmas_ctx* c, const uint16_t* knn_dev, const float* score_dev) {
     if (!c || !knn_dev || !score_dev || c->s.n < 17) return MMAS_EINVAL;
+    if (c->s.directed) return MMAS_EUNSUPPORTED;
     const Shape& s = c->s;
     hipError_t e = mmas::launch_install(c->v.dist, knn_dev, score_dev, c->v.cand, s.n, s.cl, s.beta,
                                         s.pher == MMAS_PHER_DENSE ? 1 : 0, c->v.heur, c->stream);

@@ -9,7 +9,8 @@ namespace {
 
 // flags: 1 = asymmetric, 2 = non-zero diagonal, 4 = non-positive off-diagonal.
 // 32x32 tiles; the transposed tile is staged in LDS so both reads coalesce.
-__global__ __launch_bounds__(256) void k_validate(const int32_t* __restrict__ d, int n,
+// With `directed` (ATSP) an asymmetric matrix is valid and flag 1 is not set.
+__global__ __launch_bounds__(256) void k_validate(const int32_t* __restrict__ d, int n, int directed,
                                                   uint32_t* __restrict__ flags) {
     __shared__ int32_t tile[32][33];
     const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
@@ -25,7 +26,7 @@ __global__ __launch_bounds__(256) void k_validate(const int32_t* __restrict__ d,
         if (r < n && c < n) {
             const int32_t x = d[(size_t)r * n + c];
             const int32_t y = tile[tx][j];  // d[c][r]
-            if (x != y) f |= 1u;
+            if (x != y && !directed) f |= 1u;
             if (r == c) {
                 if (x != 0) f |= 2u;
             } else if (x <= 0) {
@@ -179,7 +180,7 @@ int grid_for(size_t total, int block) {
 
 hipError_t launch_validate(const Views& v, const Shape& s, hipStream_t st) {
     const int tiles = (s.n + 31) / 32;
-    k_validate<<<dim3(tiles, tiles), dim3(32, 8), 0, st>>>(v.dist, s.n, &v.state->flags);
+    k_validate<<<dim3(tiles, tiles), dim3(32, 8), 0, st>>>(v.dist, s.n, s.directed, &v.state->flags);
     return hipGetLastError();
 }
 

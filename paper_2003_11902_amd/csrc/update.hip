@@ -1,8 +1,8 @@
 // Per-iteration kernels around construction (Alg. 1, Sec. 2.1):
 //  - choice_info = tau^alpha * eta^beta, dense and along the candidate lists;
 //  - the iteration best, the global best and the trail limits (one workgroup);
-//  - evaporation, deposit on both directions of the iteration best's edges and
-//    the [tau_min, tau_max] clamp, fused with the refresh of choice_info (the
+//  - evaporation, deposit on both directions of the iteration best's edges (on
+//    (i, succ(i)) alone for the asymmetric TSP) and the [tau_min, tau_max] clamp, fused with the refresh of choice_info (the
 //    paper's evaporation and deposition kernels in one pass; each entry is
 //    independent, so no atomics are needed).
 #include "device.hpp"
@@ -130,7 +130,7 @@ __device__ void update_dense_row(const Views& vw, const Shape& s, size_t i) {
     const mmas_device_state* st = vw.state;
     const float tmin = st->tau_min, tmax = st->tau_max, delta = st->delta;
     const float keep = 1.0f - s.rho;
-    const int si = vw.succ[i], pi = vw.pred[i];
+    const int si = vw.succ[i], pi = s.directed ? -1 : (int)vw.pred[i];
     float* trow = vw.tau + i * n;
     const float* hrow = vw.heur + i * n;
     float* crow = vw.choice + i * n;
@@ -152,7 +152,7 @@ __device__ void update_cand_row(const Views& vw, const Shape& s, size_t i) {
     const mmas_device_state* st = vw.state;
     const float tmin = st->tau_min, tmax = st->tau_max, delta = st->delta;
     const float keep = 1.0f - s.rho;
-    const int si = vw.succ[i], pi = vw.pred[i];
+    const int si = vw.succ[i], pi = s.directed ? -1 : (int)vw.pred[i];
     for (int r = threadIdx.x; r < s.cl; r += blockDim.x) {
         const size_t e = i * s.cl + r;
         const int j = vw.cand[e];
@@ -200,7 +200,8 @@ __global__ __launch_bounds__(256) void k_update_cand(Views vw, Shape s) {
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x) {
         const size_t i = e / s.cl;
         const int j = vw.cand[e];
-        const float t = evaporate_deposit(vw.tau[e], j == vw.succ[i] || j == vw.pred[i], keep, tmin, tmax, delta);
+        const bool dep = j == vw.succ[i] || (!s.directed && j == vw.pred[i]);
+        const float t = evaporate_deposit(vw.tau[e], dep, keep, tmin, tmax, delta);
         vw.tau[e] = t;
         vw.chc[e] = powi(t, s.alpha) * vw.heur[e];
     }

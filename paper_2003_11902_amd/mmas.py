@@ -47,6 +47,7 @@ MMAS_BUF_LSNN = 12
 TABU = {"bitmask": MMAS_TABU_BITMASK, "compact": MMAS_TABU_COMPACT, "list": MMAS_TABU_LIST}
 DEPOSIT = {"iteration": 0, "global": 1}
 SELECT = {"wrs": 0, "prwm": 1}
+PROBLEM = {"tsp": 0, "atsp": 1}
 PHER = {"dense": MMAS_PHER_DENSE, "candidates": MMAS_PHER_CANDIDATES}
 
 EXPORTED = (
@@ -68,6 +69,7 @@ class mmas_params(C.Structure):
         ("alpha", C.c_int32), ("beta", C.c_int32), ("rho", C.c_float),
         ("p_best", C.c_double), ("seed", C.c_uint64), ("tabu", C.c_int32),
         ("pher_mode", C.c_int32), ("ls_nn", C.c_int32), ("deposit", C.c_int32),
+        ("problem", C.c_int32),
     ]
 
 
@@ -230,11 +232,11 @@ def mmas_eval_draws(seed, it, ant, step, slot):
 
 
 def make_params(n, ants, cand_len=32, alpha=1, beta=2, rho=0.02, p_best=0.01, seed=1,
-                tabu="bitmask", pher="dense", ls_nn=0, deposit="iteration") -> mmas_params:
+                tabu="bitmask", pher="dense", ls_nn=0, deposit="iteration", problem="tsp") -> mmas_params:
     return mmas_params(n=n, ants=ants, cand_len=cand_len, alpha=alpha, beta=beta, rho=rho,
                        p_best=p_best, seed=seed, tabu=TABU.get(tabu, tabu),
                        pher_mode=PHER.get(pher, pher), ls_nn=ls_nn,
-                       deposit=DEPOSIT.get(deposit, deposit))
+                       deposit=DEPOSIT.get(deposit, deposit), problem=PROBLEM.get(problem, problem))
 
 
 def mmas_workspace_bytes(params: mmas_params) -> int:
@@ -253,7 +255,8 @@ class Colony:
     """One context: a distance matrix, its parameters and a torch-owned workspace."""
 
     def __init__(self, dist, ants, cand_len=32, alpha=1, beta=2, rho=0.02, p_best=0.01, seed=1,
-                 tabu="bitmask", pher="dense", ls_nn=0, device=None, stream=None, deposit="iteration"):
+                 tabu="bitmask", pher="dense", ls_nn=0, device=None, stream=None, deposit="iteration",
+                 problem="tsp"):
         import torch
 
         d = np.ascontiguousarray(dist, dtype=np.int32)
@@ -261,7 +264,7 @@ class Colony:
             raise ValueError("dist must be a square int32 matrix")
         self.n = int(d.shape[0])
         self.params = make_params(self.n, ants, cand_len, alpha, beta, rho, p_best, seed, tabu, pher, ls_nn,
-                                  deposit)
+                                  deposit, problem)
         self.ants = int(ants)
         ws_bytes = mmas_workspace_bytes(self.params)
         if ws_bytes == 0:

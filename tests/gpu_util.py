@@ -13,17 +13,17 @@ def say(*a):
 
 
 def make_pair(dist, ants, cand_len=32, alpha=1, beta=2, rho=0.02, seed=1, tabu="bitmask",
-              pher="dense", ls_nn=0, deposit="iteration", select="wrs"):
+              pher="dense", ls_nn=0, deposit="iteration", select="wrs", problem="tsp"):
     from oracle import oracle as O
     from paper_2003_11902_amd import mmas as M
 
     g = M.Colony(dist, ants, cand_len=cand_len, alpha=alpha, beta=beta, rho=rho, seed=seed,
-                 tabu=tabu, pher=pher, ls_nn=ls_nn, deposit=deposit)
+                 tabu=tabu, pher=pher, ls_nn=ls_nn, deposit=deposit, problem=problem)
     if select != "wrs":
         g.set_selection(select)
     o = O.Colony(dist, ants, cand_len=cand_len, alpha=alpha, beta=beta, rho=rho, seed=seed,
                  pher_mode=O.PHER_DENSE if pher == "dense" else O.PHER_CANDIDATES, ls_nn=ls_nn,
-                 deposit=deposit, select=select)
+                 deposit=deposit, select=select, problem=problem)
     return g, o
 
 

@@ -31,7 +31,8 @@ def test_exports_every_declared_symbol(M):
 
 
 def test_struct_layouts_match_header(M):
-    assert C.sizeof(M.mmas_params) == 56
+    assert C.sizeof(M.mmas_params) == 64
+    assert M.mmas_params.problem.offset == 56
     assert C.sizeof(M.mmas_device_state) == 48
     assert M.mmas_device_state.gb_len.offset == 24
 
@@ -42,6 +43,7 @@ def test_workspace_bytes(M):
     n = 1002
     # dist, heur, tau, choice: four n*n arrays dominate
     assert 18 * n * n < b < 18 * n * n + (1 << 20)  # + tours (2 n ants)
+    assert M.mmas_workspace_bytes(M.make_params(1002, 1002, 32, problem="atsp")) == b
     pc = M.make_params(18512, 64, 16, pher="candidates", ls_nn=8)
     bc = M.mmas_workspace_bytes(pc)
     assert 4 * 18512 ** 2 < bc < 4 * 18512 ** 2 + (16 << 20)
@@ -52,6 +54,7 @@ def test_workspace_bytes(M):
     dict(alpha=9), dict(beta=-1), dict(rho=0.0), dict(rho=1.0), dict(rho=float("nan")),
     dict(p_best=0.0), dict(p_best=1.0), dict(tabu=7), dict(pher=3),
     dict(pher="candidates", cand_len=0), dict(ls_nn=33), dict(n=10, ls_nn=10), dict(deposit=2), dict(tabu=3),
+    dict(problem=2), dict(problem=-1), dict(problem="atsp", ls_nn=8),
 ])
 def test_invalid_params_give_zero_workspace(M, kw):
     args = dict(n=100, ants=10, cand_len=8)
