@@ -63,6 +63,34 @@ def algorithmic_bytes(n: int, cl: int, ants: int, fallback_nodes: float) -> floa
     return ants * per_tour + 4.0 * fallback_nodes
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def copy_bandwidth_gbs(torch, mib: int = 1024, reps: int = 10) -> float:
+    """Measured device-to-device copy rate (read + write bytes per second) of
+    a plain torch copy, as a practical ceiling beside the published peak."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    sec = a.elapsed_time(b) * 1e-3 / reps
+    del src, dst
+    return 2.0 * (mib << 20) / sec / 1e9
+
+
 def cpu_baseline(dist, w, seed, budget_s):
     from oracle import oracle as O
 
@@ -90,6 +118,7 @@ def cpu_baseline(dist, w, seed, budget_s):
         if el1 >= budget_s / 3 or it1 >= 50:
             break
     return {"value": w["ants"] * it / el, "unit": "tours/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "sample": f"{it} full iterations (choice, construction of {w['ants']} tours, update) of the same "
                       f"workload, OpenMP over ants, {el:.1f} s",
             "value_1_core": w["ants"] * it1 / el1,
@@ -263,7 +292,10 @@ def main():
         it += 1
         fb_nodes.append(int(col.fallback()[1].sum()))
     torch.cuda.synchronize()
-    cons_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    cons_all = [a.elapsed_time(b) for a, b in ev]
+    cons_ms = float(np.mean(cons_all))
+    cons_median_ms = float(np.median(cons_all))
+    copy_gbs = copy_bandwidth_gbs(torch)
     nbytes = algorithmic_bytes(n, col.cl, w["ants"], float(np.mean(fb_nodes)))
     achieved = nbytes / (cons_ms * 1e-3) / 1e9
 
@@ -294,6 +326,8 @@ def main():
                                  if args.tabu == "bitmask" and args.select == "wrs" and args.cand_len is None
                                  and not args.ants else None),
                      "kernel": "k_construct" if args.select == "wrs" else "k_construct_prwm", "kernel_ms": cons_ms,
+                     "kernel_ms_median": cons_median_ms, "kernel_launches_timed": kp,
+                     "copy_measured_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                      "construct_only_tours_per_s": w["ants"] / (cons_ms * 1e-3),
                      "bytes_per_launch": nbytes},
     }
