@@ -203,12 +203,16 @@ class Colony:
                                    float(np.float32(rho)), self.pdec, seed, pher_mode, ls_nn)
         if not self._h:
             raise ValueError("orc_create rejected the arguments")
+        err = None
         if lib().orc_set_deposit(self._h, {"iteration": 0, "global": 1}.get(deposit, deposit)) != 0:
-            raise ValueError("unknown deposit mode")
-        if lib().orc_set_select(self._h, {"wrs": 0, "prwm": 1}.get(select, select)) != 0:
-            raise ValueError("unknown selection")
-        if lib().orc_set_problem(self._h, {"tsp": 0, "atsp": 1}.get(problem, problem)) != 0:
-            raise ValueError("unknown problem, or 2-opt on an asymmetric instance")
+            err = "unknown deposit mode"
+        elif lib().orc_set_select(self._h, {"wrs": 0, "prwm": 1}.get(select, select)) != 0:
+            err = "unknown selection"
+        elif lib().orc_set_problem(self._h, {"tsp": 0, "atsp": 1}.get(problem, problem)) != 0:
+            err = "unknown problem, or 2-opt on an asymmetric instance"
+        if err:
+            self.close()
+            raise ValueError(err)
         self.cl = int(lib().orc_cl(self._h))
 
     def close(self):
