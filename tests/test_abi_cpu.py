@@ -86,3 +86,16 @@ def test_status_strings(M):
     for s in (0, -1, -2, -3, -4, -5):
         assert M.status_str(s)
     assert M.status_str(-99) == "unknown status"
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the HIP library the binding refuses to import: there is no CPU
+    fallback behind it."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, MMAS_LIBRARY=str(tmp_path / "absent" / "libmmas.so"))
+    r = subprocess.run([sys.executable, "-c", "import paper_2003_11902_amd.mmas"], cwd=root, env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "ImportError" in r.stderr
