@@ -271,7 +271,8 @@ mmas_status mmas_batch_set_tabu(mmas_batch* b, int32_t tabu);
 
 /* Autotuner: times one construction launch for each ants_per_block in
  * {4, 8, 16}, the LDS table on and off, 64 or 32 lanes per ant (32 where
- * allowed) and the bitmask or the compact tabu, keeps the fastest and reports
+ * allowed) and the bitmask, compact or list tabu (where its LDS fits), keeps
+ * the fastest and reports
  * it (any pointer may be NULL). Trails are not touched. Synchronises; drops
  * a captured graph. */
 mmas_status mmas_batch_tune(mmas_batch* b, int32_t* ants_per_block, int32_t* table_bytes, int32_t* lanes_per_ant,

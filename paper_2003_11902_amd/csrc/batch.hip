@@ -261,7 +261,7 @@ mmas_status mmas_batch_tune(mmas_batch* b, int32_t* ants_per_block, int32_t* tab
         int apb, tb, lanes, tabu;
     };
     std::vector<Cand> cands;
-    for (int t : {MMAS_TABU_BITMASK, MMAS_TABU_COMPACT})
+    for (int t : {MMAS_TABU_BITMASK, MMAS_TABU_COMPACT, MMAS_TABU_LIST})
         for (int lanes : {64, 32}) {
             if (lanes == 32 && !b->pair_ok) continue;
             for (int apb : {4, 8, 16}) {
