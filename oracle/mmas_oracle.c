@@ -730,6 +730,13 @@ void orc_get_fallback(const orc_colony* c, int64_t* steps, int64_t* nodes) {
     memcpy(steps, c->fb_steps, sizeof(int64_t) * (size_t)c->ants);
     memcpy(nodes, c->fb_nodes, sizeof(int64_t) * (size_t)c->ants);
 }
+void orc_restore(orc_colony* c, const float* limits, int64_t gb_len, const uint16_t* gb_tour) {
+    c->tmin = limits[0];
+    c->tmax = limits[1];
+    c->has_gb = gb_len >= 0;
+    c->gb_len = gb_len;
+    if (gb_len >= 0) memcpy(c->gb_tour, gb_tour, sizeof(uint16_t) * (size_t)c->n);
+}
 void orc_get_limits(const orc_colony* c, float* limits) {
     limits[0] = c->tmin;
     limits[1] = c->tmax;

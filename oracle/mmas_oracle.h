@@ -135,6 +135,12 @@ int64_t orc_get_best(const orc_colony* c, uint16_t* gb_tour);
 int64_t orc_get_nn_tour(const orc_colony* c, uint16_t* tour);
 /* ib[0] = iteration-best ant, ib[1] = its length (after orc_update). */
 void orc_get_iteration_best(const orc_colony* c, int64_t* ib);
+/* Resume: the state Alg. 1 carries from one iteration to the next besides
+ * the trails (set them with orc_set_pheromone): the limits, and the global
+ * best (gb_len = -1 for none; gb_tour n entries, ignored then). Draws are
+ * keyed by the iteration number, so a colony restored after iteration t and
+ * run from t on repeats the uninterrupted run. */
+void orc_restore(orc_colony* c, const float* limits, int64_t gb_len, const uint16_t* gb_tour);
 
 /* ---- stand-alone pieces ----------------------------------------------- */
 

@@ -69,6 +69,7 @@ def lib():
         L.orc_set_heuristic.argtypes = [p, p]
         L.orc_set_heuristic.restype = C.c_int
         L.orc_get_best.argtypes = [p, p]
+        L.orc_restore.argtypes = [p, p, C.c_int64, p]
         L.orc_get_best.restype = C.c_int64
         L.orc_get_nn_tour.argtypes = [p, p]
         L.orc_get_nn_tour.restype = C.c_int64
@@ -325,6 +326,18 @@ class Colony:
         out = np.zeros(2, dtype=np.int64)
         lib().orc_get_iteration_best(self._h, _ptr(out))
         return int(out[0]), int(out[1])
+
+    def checkpoint(self):
+        """The state carried between iterations: trails, limits, global best."""
+        t, L = self.best()
+        return {"pheromone": self.pheromone(), "limits": np.array(self.limits(), dtype=np.float32),
+                "gb_len": L, "gb_tour": t if t is not None else np.zeros(self.n, np.uint16)}
+
+    def restore(self, ck):
+        self.set_pheromone(ck["pheromone"])
+        lim = np.ascontiguousarray(ck["limits"], dtype=np.float32)
+        tour = np.ascontiguousarray(ck["gb_tour"], dtype=np.uint16)
+        lib().orc_restore(self._h, _ptr(lim), int(ck["gb_len"]), _ptr(tour))
 
 
 # ---- learned heuristic ----
