@@ -226,6 +226,22 @@ mmas_status mmas_read(mmas_ctx* ctx, int which, void* host_dst, size_t bytes);
  * positive). Synchronises. Marks choice_info stale. */
 mmas_status mmas_set_pheromone(mmas_ctx* ctx, const float* host_src);
 
+/* Resume (Alg. 1 carries the trails, the trail limits and the global best
+ * from one iteration to the next; draws are keyed by the iteration number).
+ * Restores what mmas_read returns for MMAS_BUF_PHEROMONE (`tau_host`, as
+ * mmas_set_pheromone), MMAS_BUF_STATE (`state_host`: tau_min, tau_max, delta,
+ * ib_ant, ib_len, gb_len and updates are taken; nn_len and flags stay the
+ * context's own) and MMAS_BUF_GB_TOUR (`gb_tour_host`, n entries, read only
+ * when gb_len >= 0), all host memory. A context created with the same
+ * distances and parameters, restored from a run stopped after iteration t-1
+ * and driven from iteration t, repeats that run bit for bit (a learned
+ * heuristic has to be installed again). Synchronises. EINVAL for trails that
+ * are not finite and >= 0, limits that are not finite with
+ * 0 < tau_min <= tau_max, gb_len < -1, or a global-best tour that is not a
+ * permutation of 0..n-1. */
+mmas_status mmas_restore(mmas_ctx* ctx, const float* tau_host, const mmas_device_state* state_host,
+                         const uint16_t* gb_tour_host);
+
 /* Waits for all work the context has enqueued. */
 mmas_status mmas_synchronize(mmas_ctx* ctx);
 

@@ -337,6 +337,39 @@ mmas_status mmas_set_pheromone(mmas_ctx* c, const float* host_src) {
     return MMAS_OK;
 }
 
+mmas_status mmas_restore(mmas_ctx* c, const float* tau_host, const mmas_device_state* state_host,
+                         const uint16_t* gb_tour_host) {
+    if (!c || !tau_host || !state_host) return MMAS_EINVAL;
+    const mmas_device_state in = *state_host;
+    if (!std::isfinite(in.tau_min) || !std::isfinite(in.tau_max) || !(in.tau_min > 0.0f) ||
+        !(in.tau_min <= in.tau_max) || in.gb_len < -1)
+        return MMAS_EINVAL;
+    const int n = c->s.n;
+    if (in.gb_len >= 0) {
+        if (!gb_tour_host) return MMAS_EINVAL;
+        std::vector<char> seen((size_t)n, 0);
+        for (int k = 0; k < n; ++k) {
+            const int v = gb_tour_host[k];
+            if (v >= n || seen[(size_t)v]) return MMAS_EINVAL;
+            seen[(size_t)v] = 1;
+        }
+    }
+    mmas_status r = mmas_set_pheromone(c, tau_host);  // validates, copies, synchronises
+    if (r != MMAS_OK) return r;
+    mmas_device_state cur;
+    hipError_t e = hipMemcpyAsync(&cur, c->v.state, sizeof(cur), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_status(e);
+    mmas_device_state st = in;
+    st.nn_len = cur.nn_len;
+    st.flags = cur.flags;
+    e = hipMemcpyAsync(c->v.state, &st, sizeof(st), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && in.gb_len >= 0)
+        e = hipMemcpyAsync(c->v.gb_tour, gb_tour_host, 2 * (size_t)n, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return hip_status(e);
+}
+
 mmas_status mmas_set_learned_heuristic(mmas_ctx* c, const uint16_t* knn_dev, const float* score_dev) {
     if (!c || !knn_dev || !score_dev || c->s.n < 17) return MMAS_EINVAL;
     if (c->s.directed) return MMAS_EUNSUPPORTED;

@@ -60,6 +60,7 @@ EXPORTED = (
     "mmas_batch_destroy", "mmas_mlp_param_count", "mmas_mlp_packed_count", "mmas_mlp_features",
     "mmas_mlp_pack", "mmas_mlp_forward", "mmas_mlp_grad", "mmas_mlp_adam", "mmas_mlp_labels",
     "mmas_set_learned_heuristic", "mmas_last_error", "mmas_set_two_opt_launch", "mmas_batch_set_tabu",
+    "mmas_restore",
 )
 
 
@@ -122,6 +123,8 @@ def _load():
     L.mmas_read.restype = C.c_int
     L.mmas_set_pheromone.argtypes = [p, p]
     L.mmas_set_pheromone.restype = C.c_int
+    L.mmas_restore.argtypes = [p, p, p, p]
+    L.mmas_restore.restype = C.c_int
     L.mmas_destroy.argtypes = [p]
     L.mmas_destroy.restype = None
     L.mmas_eval_log.argtypes = [p, p, C.c_size_t, p]
@@ -403,6 +406,20 @@ class Colony:
     def limits(self):
         st = self.state()
         return np.float32(st.tau_min), np.float32(st.tau_max)
+
+    def checkpoint(self):
+        """Host copies of what mmas_restore takes: trails, state, global-best tour."""
+        return {"pheromone": self.pheromone(), "state": self.state(), "gb_tour": self.read(MMAS_BUF_GB_TOUR)}
+
+    def restore(self, ck):
+        t = np.ascontiguousarray(ck["pheromone"], dtype=np.float32).reshape(-1)
+        g = np.ascontiguousarray(ck["gb_tour"], dtype=np.uint16)
+        _, nbytes = self.buffer(MMAS_BUF_PHEROMONE)
+        if t.nbytes != nbytes or g.size != self.n:
+            raise ValueError("checkpoint does not match this context")
+        st = ck["state"]
+        _check(lib.mmas_restore(self._ctx, t.ctypes.data_as(C.c_void_p), C.byref(st),
+                                g.ctypes.data_as(C.c_void_p)), "mmas_restore")
 
 
 class _View(Colony):

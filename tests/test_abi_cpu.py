@@ -78,6 +78,7 @@ def test_create_rejects_before_touching_the_gpu(M):
     for name in ("mmas_prepare_choice_info", "mmas_two_opt", "mmas_update_pheromone", "mmas_synchronize"):
         assert getattr(M.lib, name)(None) == M.MMAS_EINVAL
     assert M.lib.mmas_construct(None, 0) == M.MMAS_EINVAL
+    assert M.lib.mmas_restore(None, None, None, None) == M.MMAS_EINVAL
     assert M.lib.mmas_eval_log(None, None, 5, None) == M.MMAS_EINVAL
     M.lib.mmas_destroy(None)
 
