@@ -499,7 +499,7 @@ static int select_prwm(const orc_colony* c, int cur, const uint8_t* visited, uin
                        uint32_t step, int* fallback) {
     int cl = c->cl, n = c->n;
     float u = orc_u01(orc_draw_word(c->seed, it, ant, step, 0u));
-    float w[64];
+    float* w = (float*)malloc(sizeof(float) * (size_t)(cl > 0 ? cl : 1)); /* cl may exceed 64 */
     int any = 0;
     for (int r = 0; r < cl; ++r) {
         int v = c->cand[(size_t)cur * cl + r];
@@ -507,7 +507,12 @@ static int select_prwm(const orc_colony* c, int cur, const uint8_t* visited, uin
         any |= w[r] > 0.0f;
     }
     *fallback = 0;
-    if (any) return c->cand[(size_t)cur * cl + prwm_pick(w, cl, u)];
+    if (any) {
+        const int pick = c->cand[(size_t)cur * cl + prwm_pick(w, cl, u)];
+        free(w);
+        return pick;
+    }
+    free(w);
     *fallback = 1;
     int* list = (int*)malloc(sizeof(int) * (size_t)n);
     float* wl = (float*)malloc(sizeof(float) * (size_t)n);
