@@ -282,15 +282,19 @@ def main():
     # per-kernel pass: HIP events around the construction launch on its stream
     kp = min(args.steps, 50)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(kp)]
-    fb_nodes = []
+    fb_nodes, fb_steps, curve = [], [], []
     for k in range(kp):
         col.prepare_choice_info()
         ev[k][0].record(stream)
         col.construct(it)
         ev[k][1].record(stream)
         col.update_pheromone()
+        fbs, fbn = col.fallback()
+        fb_nodes.append(int(fbn.sum()))
+        fb_steps.append(int(fbs.sum()))
+        st = col.state()
+        curve.append([it, int(st.ib_len), int(st.gb_len)])
         it += 1
-        fb_nodes.append(int(col.fallback()[1].sum()))
     torch.cuda.synchronize()
     cons_all = [a.elapsed_time(b) for a, b in ev]
     cons_ms = float(np.mean(cons_all))
@@ -330,6 +334,13 @@ def main():
                      "copy_measured_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs,
                      "construct_only_tours_per_s": w["ants"] / (cons_ms * 1e-3),
                      "bytes_per_launch": nbytes},
+    }
+    out["search"] = {
+        "fallback_step_fraction": float(np.mean(fb_steps)) / (w["ants"] * (n - 1)),
+        "fallback_nodes_per_ant": float(np.mean(fb_nodes)) / w["ants"],
+        "best_lengths": {"iterations": [c[0] for c in curve[::5]], "iteration_best": [c[1] for c in curve[::5]],
+                         "global_best": [c[2] for c in curve[::5]]},
+        "note": "from the untimed per-kernel pass that follows the timed steps",
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(dist, w, args.seed, args.cpu_budget)
