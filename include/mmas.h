@@ -242,6 +242,19 @@ mmas_status mmas_set_pheromone(mmas_ctx* ctx, const float* host_src);
 mmas_status mmas_restore(mmas_ctx* ctx, const float* tau_host, const mmas_device_state* state_host,
                          const uint16_t* gb_tour_host);
 
+/* Per-call GPU timing: with `on` != 0 every later call that enqueues GPU work
+ * (choice_info, construct, 2-opt, update) is bracketed by two hipEvents on
+ * the context's stream; off by default, and turning it off keeps what was
+ * gathered. */
+enum { MMAS_TIMING_CHOICE = 0, MMAS_TIMING_CONSTRUCT = 1, MMAS_TIMING_TWO_OPT = 2, MMAS_TIMING_UPDATE = 3,
+       MMAS_TIMING_KINDS = 4 };
+mmas_status mmas_set_timing(mmas_ctx* ctx, int32_t on);
+
+/* Milliseconds and launch counts gathered per kind (host arrays of
+ * MMAS_TIMING_KINDS entries; either may be NULL); `reset` != 0 clears them
+ * afterwards. Synchronises. */
+mmas_status mmas_read_timing(mmas_ctx* ctx, double* ms_host, int64_t* calls_host, int32_t reset);
+
 /* Waits for all work the context has enqueued. */
 mmas_status mmas_synchronize(mmas_ctx* ctx);
 

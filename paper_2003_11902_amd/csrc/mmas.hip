@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "internal.hpp"
@@ -28,6 +29,13 @@ struct mmas_ctx {
     size_t off_succ, off_pred, off_nnd;
     bool choice_stale;
     bool constructed;
+    // per-call timing (mmas_set_timing): event pairs not yet read, and the totals
+    bool timing = false;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> spare;
+    double ms[MMAS_TIMING_KINDS] = {0, 0, 0, 0};
+    int64_t calls[MMAS_TIMING_KINDS] = {0, 0, 0, 0};
+    ~mmas_ctx();
 };
 
 namespace {
@@ -116,6 +124,53 @@ T* at(char* base, size_t off, size_t len) {
 
 thread_local char g_last_error[256] = "";
 
+// Folds every pending event pair into the totals (waits for each stop event).
+hipError_t fold_timing(mmas_ctx* c) {
+    hipError_t first = hipSuccess;
+    for (auto& p : c->pending) {
+        float ms = 0.0f;
+        hipError_t e = hipEventSynchronize(p.second.second);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.second.first, p.second.second);
+        if (e == hipSuccess) {
+            c->ms[p.first] += ms;
+            c->calls[p.first] += 1;
+        } else if (first == hipSuccess) {
+            first = e;
+        }
+        c->spare.push_back(p.second);
+    }
+    c->pending.clear();
+    return first;
+}
+
+// Brackets one enqueued call with events when timing is on. Used as
+//   TimedCall t(c, kind); ...launch...; return t.done(status);
+struct TimedCall {
+    mmas_ctx* c;
+    int kind;
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    TimedCall(mmas_ctx* ctx, int k) : c(ctx), kind(k) {
+        if (!c->timing) return;
+        if (c->pending.size() >= 1024) (void)fold_timing(c);  // bounded memory
+        if (!c->spare.empty()) {
+            ev = c->spare.back();
+            c->spare.pop_back();
+        } else if (hipEventCreate(&ev.first) != hipSuccess || hipEventCreate(&ev.second) != hipSuccess) {
+            ev = {nullptr, nullptr};
+            return;
+        }
+        if (hipEventRecord(ev.first, c->stream) != hipSuccess) ev = {nullptr, nullptr};
+    }
+    void done(bool launched) {
+        if (!ev.first) return;
+        if (launched && hipEventRecord(ev.second, c->stream) == hipSuccess)
+            c->pending.push_back({kind, ev});
+        else
+            c->spare.push_back(ev);
+        ev = {nullptr, nullptr};
+    }
+};
+
 mmas_status hip_status(hipError_t e) { return e == hipSuccess ? MMAS_OK : mmas::hip_fail(e, "HIP call"); }
 
 }  // namespace
@@ -134,6 +189,15 @@ bool ctx_views(mmas_ctx* c, Views* v, Shape* s) {
     return true;
 }
 }  // namespace mmas
+
+mmas_ctx::~mmas_ctx() {
+    if (!pending.empty()) (void)hipStreamSynchronize(stream);
+    for (auto& p : pending) spare.push_back(p.second);
+    for (auto& p : spare) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+}
 
 extern "C" {
 
@@ -227,7 +291,9 @@ mmas_status mmas_create(const int32_t* dist_host, const mmas_params* p, void* de
 mmas_status mmas_prepare_choice_info(mmas_ctx* c) {
     if (!c) return MMAS_EINVAL;
     if (!c->choice_stale) return MMAS_OK;
+    TimedCall t(c, MMAS_TIMING_CHOICE);
     hipError_t e = mmas::launch_choice(c->v, c->s, c->stream);
+    t.done(e == hipSuccess);
     if (e != hipSuccess) return hip_status(e);
     c->choice_stale = false;
     return MMAS_OK;
@@ -237,7 +303,9 @@ mmas_status mmas_construct(mmas_ctx* c, uint32_t iteration) {
     if (!c) return MMAS_EINVAL;
     mmas_status r = mmas_prepare_choice_info(c);
     if (r != MMAS_OK) return r;
+    TimedCall t(c, MMAS_TIMING_CONSTRUCT);
     hipError_t e = mmas::launch_construct(c->v, c->s, iteration, c->stream);
+    t.done(e == hipSuccess);
     if (e != hipSuccess) return hip_status(e);
     c->constructed = true;
     return MMAS_OK;
@@ -281,14 +349,18 @@ mmas_status mmas_two_opt(mmas_ctx* c) {
     if (!c) return MMAS_EINVAL;
     if (c->s.ls_nn <= 0) return MMAS_EUNSUPPORTED;
     if (!c->constructed) return MMAS_ESTATE;
+    TimedCall t(c, MMAS_TIMING_TWO_OPT);
     hipError_t e = mmas::launch_two_opt(c->v, c->s, reinterpret_cast<const int32_t*>(c->ws + c->off_nnd), c->stream);
+    t.done(e == hipSuccess);
     return hip_status(e);
 }
 
 mmas_status mmas_update_pheromone(mmas_ctx* c) {
     if (!c) return MMAS_EINVAL;
     if (!c->constructed) return MMAS_ESTATE;
+    TimedCall t(c, MMAS_TIMING_UPDATE);
     hipError_t e = mmas::launch_update(c->v, c->s, c->stream);
+    t.done(e == hipSuccess);
     if (e != hipSuccess) return hip_status(e);
     c->choice_stale = false;  // refreshed by the fused pass
     return MMAS_OK;
@@ -384,6 +456,26 @@ mmas_status mmas_set_learned_heuristic(mmas_ctx* c, const uint16_t* knn_dev, con
 mmas_status mmas_synchronize(mmas_ctx* c) {
     if (!c) return MMAS_EINVAL;
     return hip_status(hipStreamSynchronize(c->stream));
+}
+
+mmas_status mmas_set_timing(mmas_ctx* c, int32_t on) {
+    if (!c) return MMAS_EINVAL;
+    c->timing = on != 0;
+    return MMAS_OK;
+}
+
+mmas_status mmas_read_timing(mmas_ctx* c, double* ms_host, int64_t* calls_host, int32_t reset) {
+    if (!c) return MMAS_EINVAL;
+    const hipError_t e = fold_timing(c);
+    for (int k = 0; k < MMAS_TIMING_KINDS; ++k) {
+        if (ms_host) ms_host[k] = c->ms[k];
+        if (calls_host) calls_host[k] = c->calls[k];
+        if (reset) {
+            c->ms[k] = 0.0;
+            c->calls[k] = 0;
+        }
+    }
+    return hip_status(e);
 }
 
 void mmas_destroy(mmas_ctx* c) { delete c; }

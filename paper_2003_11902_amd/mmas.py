@@ -60,7 +60,7 @@ EXPORTED = (
     "mmas_batch_destroy", "mmas_mlp_param_count", "mmas_mlp_packed_count", "mmas_mlp_features",
     "mmas_mlp_pack", "mmas_mlp_forward", "mmas_mlp_grad", "mmas_mlp_adam", "mmas_mlp_labels",
     "mmas_set_learned_heuristic", "mmas_last_error", "mmas_set_two_opt_launch", "mmas_batch_set_tabu",
-    "mmas_restore",
+    "mmas_restore", "mmas_set_timing", "mmas_read_timing",
 )
 
 
@@ -125,6 +125,10 @@ def _load():
     L.mmas_set_pheromone.restype = C.c_int
     L.mmas_restore.argtypes = [p, p, p, p]
     L.mmas_restore.restype = C.c_int
+    L.mmas_set_timing.argtypes = [p, C.c_int32]
+    L.mmas_set_timing.restype = C.c_int
+    L.mmas_read_timing.argtypes = [p, p, p, C.c_int32]
+    L.mmas_read_timing.restype = C.c_int
     L.mmas_destroy.argtypes = [p]
     L.mmas_destroy.restype = None
     L.mmas_eval_log.argtypes = [p, p, C.c_size_t, p]
@@ -406,6 +410,17 @@ class Colony:
     def limits(self):
         st = self.state()
         return np.float32(st.tau_min), np.float32(st.tau_max)
+
+    def set_timing(self, on=True):
+        _check(lib.mmas_set_timing(self._ctx, 1 if on else 0), "mmas_set_timing")
+
+    def read_timing(self, reset=False):
+        """{kind: (milliseconds, launches)} for choice, construct, two_opt, update."""
+        ms = np.zeros(4, dtype=np.float64)
+        calls = np.zeros(4, dtype=np.int64)
+        _check(lib.mmas_read_timing(self._ctx, ms.ctypes.data_as(C.c_void_p), calls.ctypes.data_as(C.c_void_p),
+                                    1 if reset else 0), "mmas_read_timing")
+        return {k: (float(ms[i]), int(calls[i])) for i, k in enumerate(("choice", "construct", "two_opt", "update"))}
 
     def checkpoint(self):
         """Host copies of what mmas_restore takes: trails, state, global-best tour."""

@@ -79,6 +79,8 @@ def test_create_rejects_before_touching_the_gpu(M):
         assert getattr(M.lib, name)(None) == M.MMAS_EINVAL
     assert M.lib.mmas_construct(None, 0) == M.MMAS_EINVAL
     assert M.lib.mmas_restore(None, None, None, None) == M.MMAS_EINVAL
+    assert M.lib.mmas_set_timing(None, 1) == M.MMAS_EINVAL
+    assert M.lib.mmas_read_timing(None, None, None, 0) == M.MMAS_EINVAL
     assert M.lib.mmas_eval_log(None, None, 5, None) == M.MMAS_EINVAL
     M.lib.mmas_destroy(None)
 

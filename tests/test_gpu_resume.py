@@ -84,3 +84,34 @@ def test_restore_rejects_bad_checkpoints(gpu):
     assert e.value.status == M.MMAS_EINVAL
     g.restore(ck)  # the good checkpoint still restores
     assert g.best()[1] == ck["state"].gb_len
+
+
+def test_per_call_timing(gpu):
+    """mmas_set_timing: launch counts per kind and GPU milliseconds that agree
+    with HIP events taken around the same construction calls."""
+    from paper_2003_11902_amd import mmas as M
+    _, d = I.make_instance("uniform", 400, seed=6)
+    g = M.Colony(d, 400, cand_len=16, ls_nn=8)
+    g.iterate(0)
+    assert all(v == (0.0, 0) for v in g.read_timing().values())  # off by default
+    g.set_timing(True)
+    ev = []
+    for it in range(1, 6):
+        a, b = gpu.cuda.Event(enable_timing=True), gpu.cuda.Event(enable_timing=True)
+        g.prepare_choice_info()
+        a.record(g.stream)
+        g.construct(it)
+        b.record(g.stream)
+        g.two_opt()
+        g.update_pheromone()
+        ev.append((a, b))
+    gpu.cuda.synchronize()
+    t = g.read_timing(reset=True)
+    assert t["construct"][1] == 5 and t["two_opt"][1] == 5 and t["update"][1] == 5
+    assert t["choice"][1] == 0  # the fused update keeps choice_info current
+    ref = sum(a.elapsed_time(b) for a, b in ev)
+    assert t["construct"][0] > 0 and abs(t["construct"][0] - ref) <= 0.2 * ref + 0.05
+    assert g.read_timing()["construct"] == (0.0, 0)  # reset
+    g.set_timing(False)
+    g.iterate(6)
+    assert g.read_timing()["construct"] == (0.0, 0)
