@@ -1,4 +1,4 @@
-"""Checkpoint and resume on the GPU (mmas_restore): a context restored from
+"""Runtime services on the GPU. Checkpoint and resume (mmas_restore): a context restored from
 a run stopped after iteration t-1 and driven from iteration t repeats the
 uninterrupted run bit for bit, and both equal the oracle."""
 import numpy as np
