@@ -170,8 +170,10 @@ mmas_status mmas_construct(mmas_ctx* ctx, uint32_t iteration);
  * ants per workgroup, else 64 is used). `waves_per_ant`: 1, 2, 4, 8 or 16
  * waves serve each ant (one workgroup per ant: the first wave takes the
  * steps, all of them share every all-city fallback; ignored with 32 lanes
- * per ant); 0 (default) = the largest power of two up to 16 such that
- * ants x waves fit the GPU's SIMDs once. EINVAL for other values. */
+ * per ant); 0 (default): several only where the all-city fallback dominates
+ * (n >= 8192: the largest power of two up to 16 such that ants x waves fit
+ * the GPU's SIMDs once; no candidate list with the compact or list tabu and
+ * n >= 512: 4), else 1. EINVAL for other values. */
 mmas_status mmas_set_launch(mmas_ctx* ctx, int32_t ants_per_block, int32_t table_rows, int32_t lanes_per_ant,
                             int32_t waves_per_ant);
 

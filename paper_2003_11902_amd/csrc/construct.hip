@@ -908,15 +908,25 @@ hipError_t launch_t(const Views& v, const Shape& s0, uint32_t it, hipStream_t st
     return hipGetLastError();
 }
 
-// Waves per ant for the construction: the launch option, or (0) as many as
-// the SIMDs left over by one wave per ant allow, a power of two up to 16.
+// Waves per ant for the construction: the launch option, or (0) a choice by
+// where the all-city fallback dominates the step, the only part the helper
+// waves share. With n >= 8192 (long fallbacks) and SIMDs to spare: as many
+// as the SIMDs left over by one wave per ant allow, a power of two up to 16.
+// Without a candidate list and with a tabu that keeps the unvisited cities
+// listed (compact, list) at n >= 512: four. Otherwise one: the per-step
+// barriers then cost more than the shared fallbacks save (measured at
+// n = 198, 1002 and 3795 with and without lists).
 int construct_waves(const Shape& s) {
     if (s.construct_waves > 0) return s.construct_waves;
-    // four SIMDs per compute unit
-    const int simds = device_attr(g_simds, hipDeviceAttributeMultiprocessorCount, 4, 0);
-    int w = 1;
-    while (w < 16 && 2 * w * s.ants <= simds) w *= 2;
-    return w;
+    if (s.n >= 8192) {
+        // four SIMDs per compute unit
+        const int simds = device_attr(g_simds, hipDeviceAttributeMultiprocessorCount, 4, 0);
+        int w = 1;
+        while (w < 16 && 2 * w * s.ants <= simds) w *= 2;
+        return w;
+    }
+    if (s.cl == 0 && s.tabu != MMAS_TABU_BITMASK && s.n >= 512) return 4;
+    return 1;
 }
 
 template <int kTabu, int kPher>
