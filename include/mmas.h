@@ -40,7 +40,7 @@ extern "C" {
 typedef enum mmas_status {
     MMAS_OK = 0,
     MMAS_EINVAL = -1,      /* an argument or the distance matrix is invalid */
-    MMAS_EUNSUPPORTED = -2,/* valid, but outside what this build implements */
+    MMAS_EUNSUPPORTED = -2,/* valid, but outside what this library implements */
     MMAS_ENOSPACE = -3,    /* workspace smaller than mmas_workspace_bytes() */
     MMAS_EHIP = -4,        /* a HIP runtime call or a kernel failed */
     MMAS_ESTATE = -5       /* call out of order (e.g. update before construct) */
