@@ -294,6 +294,20 @@ __device__ void gather_unvisited_block(const BitmaskTabu& tabu, int n, uint16_t*
     }
 }
 
+// A wave's best (key code, lowest city) packed so that the larger value is
+// the better one; 0 if the wave saw no city.
+__device__ __forceinline__ unsigned long long share_result(uint32_t bcode, uint32_t bnode) {
+    const uint32_t bc = wave_max_u32<4>(bcode);
+    if (bc == 0u) return 0ull;
+    const uint64_t tied = __ballot(bcode == bc);
+    uint32_t node;
+    if (__popcll(tied) == 1)
+        node = (uint32_t)__builtin_amdgcn_readlane((int)bnode, __ffsll((unsigned long long)tied) - 1);
+    else
+        node = wave_min_u32<4>(bcode == bc ? bnode : kNone);
+    return ((unsigned long long)bc << 32) | (unsigned long long)(~node);
+}
+
 // This wave's share of a workgroup-wide fallback (entries wave*64 + lane,
 // then every 64*waves): its best (key code, lowest city), packed so that the
 // larger value is the better one; 0 if the wave saw no city.
@@ -321,15 +335,35 @@ __device__ __forceinline__ unsigned long long fallback_share(const uint16_t* lis
             keep_best(ord_key(key), v[u], bcode, bnode);
         }
     }
-    const uint32_t bc = wave_max_u32<4>(bcode);
-    if (bc == 0u) return 0ull;
-    const uint64_t tied = __ballot(bcode == bc);
-    uint32_t node;
-    if (__popcll(tied) == 1)
-        node = (uint32_t)__builtin_amdgcn_readlane((int)bnode, __ffsll((unsigned long long)tied) - 1);
-    else
-        node = wave_min_u32<4>(bcode == bc ? bnode : kNone);
-    return ((unsigned long long)bc << 32) | (unsigned long long)(~node);
+    return share_result(bcode, bnode);
+}
+
+// The same share laid out by draw blocks instead of list entries: a lane
+// takes the block of slots 4b .. 4b+3 (b from the first block holding slot
+// cl, wave*64 + lane, then every 64*waves), computes that Philox block once
+// and keys each of its cities (slot - cl) that is unvisited. While most
+// cities are unvisited this needs a quarter of the blocks of the list layout;
+// the keys, and so the winner, are the same.
+template <class T, class W>
+__device__ __forceinline__ unsigned long long fallback_share_blocks(const T& tabu, int n, const W& weight, int cl,
+                                                                    uint64_t seed, uint32_t it, uint32_t ant,
+                                                                    uint32_t step, int lane, int wv, int nw) {
+    uint32_t bcode = 0u, bnode = kNone;
+    const int b_lo = cl >> 2, b_hi = (cl + n - 1) >> 2;  // blocks holding slots cl .. cl + n - 1
+    for (int b0 = b_lo + wv * kWave; b0 <= b_hi; b0 += kWave * nw) {
+        const int b = b0 + lane;
+        if (b <= b_hi) {
+            const Words4 blk = draw_block(seed, it, ant, step, (uint32_t)(4 * b));
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int v = 4 * b + j - cl;
+                if (v < 0 || v >= n || tabu.visited((uint32_t)v)) continue;
+                const float key = log_u01(u01(blk.w[j])) / weight((uint32_t)v);
+                keep_best(ord_key(key), (uint32_t)v, bcode, bnode);
+            }
+        }
+    }
+    return share_result(bcode, bnode);
 }
 
 // LDS layout of one workgroup: the candidate table of cities 0..R-1 (ids,
@@ -475,14 +509,22 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
                 } else {
                     L = wl->L;
                     list = tabu.list();
+                    if constexpr (kTabu == MMAS_TABU_LIST) tabu.L = L;  // the helpers' copy of the length
                 }
+                // by draw blocks while they are cheaper: a block costs about a
+                // Philox and four keys, a listed city a Philox and one key
+                const bool by_blocks = kTabu != MMAS_TABU_BITMASK && 46 * L > 25 * n;
                 unsigned long long mine;
                 if constexpr (kPher == MMAS_PHER_DENSE) {
                     const DenseWeight wt{vw.choice + (size_t)fcur * n};
-                    mine = fallback_share(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw);
+                    mine = by_blocks
+                               ? fallback_share_blocks(tabu, n, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw)
+                               : fallback_share(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw);
                 } else {
                     const CandWeight wt{dist + (size_t)fcur * n, tmin_a, s.beta};
-                    mine = fallback_share(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw);
+                    mine = by_blocks
+                               ? fallback_share_blocks(tabu, n, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw)
+                               : fallback_share(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw);
                 }
                 if (lane == 0) wl->res[wv] = mine;
                 __syncthreads();
