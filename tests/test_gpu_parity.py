@@ -255,11 +255,13 @@ def test_roulette_wheel_needs_bitmask(gpu):
 
 
 @pytest.mark.parametrize("tabu", ["list", "compact"])
-@pytest.mark.parametrize("cl,waves,pher", [(0, 0, "dense"), (0, 16, "dense"), (1, 4, "dense"), (3, 2, "candidates")])
+@pytest.mark.parametrize("cl,waves,pher", [(0, 0, "dense"), (0, 16, "dense"), (1, 4, "dense"), (3, 2, "candidates"),
+                                             (0, 1, "dense"), (2, 1, "candidates")])
 def test_wide_fallback_by_draw_blocks(gpu, tabu, cl, waves, pher):
-    """Fallbacks shared by several waves per ant, keyed by draw blocks while
-    most cities are unvisited and by list entries later: tours and trails
-    equal the oracle's (no list or short lists, so fallbacks start early)."""
+    """Fallbacks of one wave per ant (keyed by list entries) or of several
+    waves sharing them (keyed by draw blocks while most cities are unvisited,
+    by list entries later): tours and trails equal the oracle's (no list or
+    short lists, so fallbacks start early)."""
     _, d = I.make_instance("clustered", 600, seed=41, clusters=5, sigma=400.0)
     say(f"wide fallback {tabu} cl {cl} waves {waves} {pher}")
     run_parity(d, 3, ants=40, cand_len=cl, rho=0.1, seed=2, tabu=tabu, pher=pher, launch=(0, -1, 64, waves))
