@@ -210,10 +210,13 @@ mmas_status mmas_set_two_opt_launch(mmas_ctx* ctx, int32_t waves_per_ant);
  * of the iteration best's edges (MMAS_PROBLEM_ATSP: on (i, succ(i)) only;
  * with MMAS_DEPOSIT_GLOBAL_BEST: 1/C_gb on the global best's), then
  * min(., tau_max) on every stored trail;
- * choice_info is refreshed in the same pass. ESTATE before a construct. */
+ * choice_info is refreshed in the same pass. ESTATE unless a construct came
+ * after the previous update (Alg. 1 deposits each iteration's tours once). */
 mmas_status mmas_update_pheromone(mmas_ctx* ctx);
 
-/* Global best so far. Synchronises. `tour_host` (n int32) may be NULL.
+/* Global best so far: the shortest tour of all iterations, which Alg. 1
+ * keeps beside the trails and uses for the limits (Sec. 2.1). Synchronises.
+ * `tour_host` (n int32) may be NULL.
  * *len_host = -1 while there is no global best. */
 mmas_status mmas_best(mmas_ctx* ctx, int32_t* tour_host, int64_t* len_host);
 
@@ -322,6 +325,8 @@ mmas_status mmas_batch_iteration(mmas_batch* b, uint32_t* iteration);
  * mmas_best and mmas_buffer. Do not drive it with the per-iteration calls. */
 mmas_status mmas_batch_context(mmas_batch* b, int32_t index, mmas_ctx** ctx);
 
+/* Waits for the batch's enqueued steps, then frees it and its contexts (not
+ * the workspace). NULL is a no-op. */
 void mmas_batch_destroy(mmas_batch* b);
 
 /* ---- learned heuristic -----------------------------------------------------

@@ -362,6 +362,9 @@ mmas_status mmas_batch_context(mmas_batch* b, int32_t index, mmas_ctx** ctx) {
 
 void mmas_batch_destroy(mmas_batch* b) {
     if (!b) return;
+    // the caller may free the workspace right after this call: let every
+    // step already enqueued (a graph replay included) finish first
+    (void)hipStreamSynchronize(b->stream);
     drop_graph(b);
     for (mmas_ctx* c : b->ctx) mmas_destroy(c);
     delete b;

@@ -363,6 +363,7 @@ mmas_status mmas_update_pheromone(mmas_ctx* c) {
     t.done(e == hipSuccess);
     if (e != hipSuccess) return hip_status(e);
     c->choice_stale = false;  // refreshed by the fused pass
+    c->constructed = false;   // these tours have deposited; the next update needs new ones
     return MMAS_OK;
 }
 
@@ -478,7 +479,12 @@ mmas_status mmas_read_timing(mmas_ctx* c, double* ms_host, int64_t* calls_host, 
     return hip_status(e);
 }
 
-void mmas_destroy(mmas_ctx* c) { delete c; }
+void mmas_destroy(mmas_ctx* c) {
+    if (!c) return;
+    // the caller may free the workspace right after this call
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
 
 const char* mmas_last_error(void) { return g_last_error; }
 

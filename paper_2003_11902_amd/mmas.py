@@ -258,6 +258,19 @@ _DTYPES = {
 }
 
 
+def _adopt(ws, stream):
+    """Hands the workspace (allocated on the caller's current stream) to the
+    stream the library enqueues on: that stream first waits for the current
+    one, and the caching allocator does not reuse the block until the work
+    enqueued on it has finished."""
+    import torch
+
+    cur = torch.cuda.current_stream(ws.device)
+    if stream.cuda_stream != cur.cuda_stream:
+        stream.wait_stream(cur)
+        ws.record_stream(stream)
+
+
 class Colony:
     """One context: a distance matrix, its parameters and a torch-owned workspace."""
 
@@ -279,6 +292,7 @@ class Colony:
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.ws = torch.empty(ws_bytes, dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _adopt(self.ws, self.stream)
         self._ctx = C.c_void_p()
         with torch.cuda.device(self.device):
             st = lib.mmas_create(d.ctypes.data_as(C.c_void_p), C.byref(self.params),
@@ -469,6 +483,7 @@ class Batch:
         self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
         # a stream of its own (default priority): the null stream cannot be captured
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        _adopt(self.ws, self.stream)
         ptrs = (C.c_void_p * self.count)(*[d.ctypes.data_as(C.c_void_p) for d in self.dists])
         self._h = C.c_void_p()
         with torch.cuda.device(self.device):

@@ -115,3 +115,45 @@ def test_per_call_timing(gpu):
     g.set_timing(False)
     g.iterate(6)
     assert g.read_timing()["construct"] == (0.0, 0)
+
+
+def test_update_needs_new_tours(gpu):
+    """Alg. 1 deposits each iteration's tours once: a second update without a
+    construction in between is refused, and the trails stay as they were."""
+    from paper_2003_11902_amd import mmas as M
+    _, d = I.make_instance("uniform", 60, seed=8)
+    g = M.Colony(d, 12, cand_len=8)
+    g.iterate(0)
+    tau = g.pheromone().copy()
+    with pytest.raises(M.MmasError) as e:
+        g.update_pheromone()
+    assert e.value.status == M.MMAS_ESTATE
+    assert np.array_equal(g.pheromone().view(np.uint32), tau.view(np.uint32))
+    g.iterate(1)  # a construction re-arms it
+
+
+def test_close_waits_for_enqueued_work(gpu):
+    """Destroying a batch or a context right after an unsynchronised step
+    leaves no work running on the stream that uses the workspace, and the
+    workspace block is not handed out again before that work is done."""
+    from paper_2003_11902_amd import mmas as M
+    dists, params = [], []
+    for k in range(6):
+        _, d = I.make_instance("uniform", 300 + 50 * k, seed=40 + k)
+        dists.append(d)
+        params.append(M.make_params(d.shape[0], d.shape[0], cand_len=16, rho=0.05, seed=1 + k))
+    b = M.Batch(dists, params)
+    b.capture()
+    for _ in range(3):
+        b.step()
+    st = b.stream
+    b.close()
+    assert st.query(), "the batch stream still had work after mmas_batch_destroy"
+    del b
+    side = gpu.cuda.Stream()
+    _, d = I.make_instance("clustered", 500, seed=9, clusters=4, sigma=300.0)
+    g = M.Colony(d, 500, cand_len=32, stream=side)
+    g.prepare_choice_info()
+    g.construct(0)
+    g.close()
+    assert side.query(), "the context's stream still had work after mmas_destroy"
