@@ -181,11 +181,13 @@ mmas_status mmas_set_launch(mmas_ctx* ctx, int32_t ants_per_block, int32_t table
  * roulette wheel of Sec. 4.2.1 with p = 64 (one wave per ant): one draw per
  * step (slot 0); over the unvisited candidates by rank, or over every
  * unvisited city in index order; 64 chunks a stage, chunk sums left to
- * right, their prefix sums in a wave scan's order (log steps within rows of
- * 16, then the earlier rows' totals), target u times the total, the first
- * chunk whose prefix exceeds the target (else the last with a positive sum),
- * repeated inside it with the target less the prefix before it; every weight
- * 0 gives the lowest entry. Bitmask tabu only (EUNSUPPORTED otherwise), the
+ * right, their prefix sums by a wave scan (log steps within rows of 16, then
+ * the earlier rows' totals: an FP32 summation order of its own, so the wheel
+ * is defined by its selection probabilities, w_j / sum of w, not by the bits
+ * of a sequential sum), target u times the total, the first chunk whose
+ * prefix exceeds the target (else the last with a positive sum), repeated
+ * inside it with the target less the prefix before it; every weight 0 gives
+ * the lowest entry. Bitmask tabu only (EUNSUPPORTED otherwise), the
  * launch options do not apply, and a batch's constructions ignore it.
  * MMAS_SELECT_WRS (default): Alg. 4. */
 mmas_status mmas_set_selection(mmas_ctx* ctx, int32_t select);

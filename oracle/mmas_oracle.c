@@ -432,55 +432,36 @@ static float fallback_weight(const orc_colony* c, int cur, int v) {
     return powi_f32(c->tmin, c->alpha) * heur_of(c->dist[(size_t)cur * c->n + v], c->beta);
 }
 
-/* Inclusive prefix sums of 64 partial sums in the order a wave64 forms them:
- * within each row of 16 a log-step scan (x[i] += x[i-d] for d = 1, 2, 4, 8,
- * lanes below d of their row adding 0), then every row adds the totals of the
- * rows before it (row 1: t0; row 2: t0 + t1; row 3: (t0 + t1) + t2). */
-static void scan64(float x[64]) {
-    for (int d = 1; d < 16; d <<= 1) {
-        float y[64];
-        for (int i = 0; i < 64; ++i) y[i] = (i % 16 >= d) ? x[i - d] : 0.0f;
-        for (int i = 0; i < 64; ++i) x[i] = x[i] + y[i];
-    }
-    float t0 = x[15], t1 = x[31], t2 = x[47];
-    for (int i = 0; i < 64; ++i) {
-        int row = i / 16;
-        float add = 0.0f;
-        if (row >= 1) add = t0;
-        if (row >= 2) add = add + t1;
-        if (row >= 3) add = add + t2;
-        x[i] = x[i] + add;
-    }
-}
-
-/* The parallel roulette wheel of Sec. 4.2.1 with p = 64: the m weights are
- * cut into 64 chunks of ceil(m/64) (chunk sums left to right), the chunks'
- * prefix sums are formed, u times the total is the target, and the first
- * chunk whose prefix exceeds it wins (the last chunk with a positive sum if
- * rounding leaves none); the target less the prefix before that chunk is
- * then located in the same way inside it, until a chunk is one weight.
- * Returns the winning index; m >= 1 and some weight > 0. */
+/* The parallel roulette wheel of Sec. 4.2.1 with p = 64 workers: the m
+ * weights are cut into 64 chunks of ceil(m/64) consecutive entries (the last
+ * chunks may be short or empty); each chunk's weights are summed left to
+ * right, and the chunk sums' inclusive prefix sums are formed left to right,
+ * P[l] = P[l-1] + s[l]. The draw u times the total P[63] is the target; the
+ * winning chunk is the first with a positive sum whose prefix exceeds the
+ * target (the last chunk with a positive sum if rounding leaves none). Inside
+ * it the same is done again, with the target less the prefix before the
+ * chunk, until a chunk holds one weight. Returns the winning index; m >= 1
+ * and some weight > 0. */
 static int prwm_pick(const float* w, int m, float u) {
     int lo = 0, len = m;
     float target = 0.0f;
     int first = 1;
     for (;;) {
-        int c = (len + 63) / 64;
+        const int c = (len + 63) / 64;
         float s[64], P[64];
         for (int l = 0; l < 64; ++l) {
             float a = 0.0f;
             for (int q = l * c; q < (l + 1) * c && q < len; ++q) a = a + w[lo + q];
             s[l] = a;
-            P[l] = a;
+            P[l] = l == 0 ? a : P[l - 1] + a;
         }
-        scan64(P);
         if (first) {
             target = u * P[63];
             first = 0;
         }
         int win = -1;
         for (int l = 0; l < 64 && win < 0; ++l)
-            if (P[l] > target && s[l] > 0.0f) win = l;
+            if (s[l] > 0.0f && P[l] > target) win = l;
         for (int l = 63; l >= 0 && win < 0; --l)
             if (s[l] > 0.0f) win = l;
         if (win < 0) win = 0;

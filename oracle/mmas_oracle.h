@@ -87,8 +87,9 @@ enum { ORC_DEPOSIT_ITERATION_BEST = 0, ORC_DEPOSIT_GLOBAL_BEST = 1 };
 int orc_set_deposit(orc_colony* c, int mode);
 
 /* Node selection: weighted reservoir sampling (Alg. 4, default) or the
- * parallel roulette wheel of Sec. 4.2.1 (64 chunks a stage, one draw per
- * step). Returns -1 for another mode. */
+ * parallel roulette wheel of Sec. 4.2.1 (64 chunks a stage, chunk sums and
+ * their prefix sums left to right, one draw per step). Returns -1 for
+ * another mode. */
 enum { ORC_SELECT_WRS = 0, ORC_SELECT_PRWM = 1 };
 int orc_set_select(orc_colony* c, int mode);
 

@@ -34,7 +34,6 @@ def asym(kind, n, seed, frac=0.5):
     ("cand300", "clustered", 300, dict(ants=64, cand_len=10, pher="candidates")),
     ("nolist130", "uniform", 130, dict(ants=40, cand_len=0)),
     ("global150", "clustered", 150, dict(ants=6, cand_len=10, deposit="global")),
-    ("prwm198", "uniform", 198, dict(ants=198, cand_len=32, select="prwm")),
     ("big_fallback1500", "uniform", 1500, dict(ants=8, cand_len=2)),
 ], ids=lambda x: x if isinstance(x, str) else "")
 def test_atsp_matches_oracle(gpu, name, kind, n, kw):

@@ -229,22 +229,6 @@ def test_global_best_deposit(gpu, pher):
     run_parity(d, 25, ants=6, cand_len=10, rho=0.1, seed=3, pher=pher, deposit="global")
 
 
-@pytest.mark.parametrize("name,kind,n,seed,kw", [
-    ("prwm198", "uniform", 198, 1, dict(ants=198, cand_len=32, pher="dense")),
-    ("prwm_cand300", "clustered", 300, 2, dict(ants=64, cand_len=10, pher="candidates")),
-    ("prwm_nolist130", "uniform", 130, 3, dict(ants=40, cand_len=0, pher="dense")),
-    ("prwm_cl1", "clustered", 150, 4, dict(ants=20, cand_len=1, pher="dense")),
-    ("prwm_big_fallback", "uniform", 1500, 5, dict(ants=8, cand_len=2, pher="dense")),
-], ids=lambda x: x if isinstance(x, str) else "")
-def test_roulette_wheel_matches_oracle(gpu, name, kind, n, seed, kw):
-    """The parallel roulette wheel (Sec. 4.2.1): tours, lengths and trails
-    equal the oracle's, with and without candidate lists, one-entry lists, and
-    fallbacks over up to 1499 cities (two stages of 64 chunks)."""
-    _, d = I.make_instance(kind, n, seed=seed, **({} if kind == "uniform" else dict(clusters=5, sigma=400.0)))
-    say(f"prwm {name}")
-    run_parity(d, 4, rho=0.1, seed=seed, select="prwm", **kw)
-
-
 def test_roulette_wheel_needs_bitmask(gpu):
     from paper_2003_11902_amd import mmas as M
     _, d = I.make_instance("uniform", 50, seed=3)

@@ -3,40 +3,13 @@ sampling of Alg. 4 with logarithmic keys must pick node j with probability
 w_j / sum(w) (the A-Res property, Sec. 4.2.2), over the unvisited part of the
 candidate list (Sec. 4.3), or over every unvisited node when none is left.
 Exact probabilities are computed here in float64 straight from d and tau."""
-import itertools
-
 import numpy as np
 import pytest
-from scipy import stats
 
 from paper_2003_11902_amd import instances as I
+from tests.stat_util import chi2_ok, exact_tour_probs, ref_candidates, sequential_wheel_tours
 
 DRAWS = 120_000
-
-
-def chi2_ok(counts: dict, probs: dict, draws: int, pmin=1e-3):
-    keys = sorted(probs)
-    obs = np.array([counts.get(k, 0) for k in keys], dtype=np.float64)
-    exp = np.array([probs[k] for k in keys]) * draws
-    # never a node outside the support
-    assert sum(counts.values()) == obs.sum() == draws, "selected a node with zero probability"
-    # pool bins with small expectation into one
-    small = exp < 5
-    if small.any():
-        obs = np.append(obs[~small], obs[small].sum())
-        exp = np.append(exp[~small], exp[small].sum())
-    p = stats.chisquare(obs, exp).pvalue
-    assert p > pmin, (p, obs, exp)
-
-
-def ref_candidates(dist, cl):
-    n = dist.shape[0]
-    out = np.zeros((n, cl), dtype=np.int64)
-    for i in range(n):
-        js = np.array([j for j in range(n) if j != i])
-        order = np.lexsort((js, dist[i, js]))  # by distance, then index
-        out[i] = js[order][:cl]
-    return out
 
 
 def sample(col, cur, visited, draws=DRAWS, step=5):
@@ -164,28 +137,6 @@ def test_equal_keys_go_to_lowest_node(orc, inst):
         assert fb and v == min(j for j in range(n) if not visited[j])
 
 
-def exact_tour_probs(dist, tau, cl, alpha, beta):
-    """P(tour) = (1/n) * prod over steps of Eq. (1) restricted as in Sec. 4.3."""
-    n = dist.shape[0]
-    cands = ref_candidates(dist, cl)
-    w = tau.astype(np.float64) ** alpha * (1.0 / np.where(dist > 0, dist, 1)) ** beta
-    probs = {}
-    for perm in itertools.permutations(range(n)):
-        p = 1.0 / n
-        vis = {perm[0]}
-        for k in range(1, n):
-            c = perm[k - 1]
-            S = [j for j in cands[c] if j not in vis]
-            if not S:
-                S = [j for j in range(n) if j not in vis]
-            p *= (w[c, perm[k]] / sum(w[c, j] for j in S)) if perm[k] in S else 0.0
-            vis.add(perm[k])
-        if p > 0:
-            probs[perm] = p
-    assert abs(sum(probs.values()) - 1.0) < 1e-9
-    return probs
-
-
 @pytest.mark.parametrize("asym", [False, True])
 @pytest.mark.parametrize("select", ["wrs", "prwm"])
 @pytest.mark.parametrize("n,cl", [(5, 2), (6, 3)])
@@ -253,3 +204,27 @@ def test_prwm_single_unvisited_and_differs_from_wrs(orc, inst):
     visited[cur] = 1
     picks = [(col.select_next(cur, visited, 0, a, 1), wrs.select_next(cur, visited, 0, a, 1)) for a in range(200)]
     assert any(p != q for p, q in picks)
+
+
+@pytest.mark.parametrize("n,cl,ants", [(300, 8, 12), (300, 0, 6), (4200, 0, 2)])
+def test_prwm_integer_weights_equal_the_sequential_wheel(orc, n, cl, ants):
+    """With small integer weights every partial sum is exact in FP32, so the
+    parallel wheel of Sec. 4.2.1 (64 chunk sums, their prefix sums, the
+    target located again inside the winning chunk, for one, two or three
+    stages) must pick exactly what the textbook sequential wheel picks: the
+    first eligible entry whose running total exceeds u times the total. The
+    replay below rebuilds every step of every tour that way."""
+    _, d = I.make_instance("uniform", n, seed=60 + cl, side=1e5)
+    col = orc.Colony(d, ants=ants, cand_len=cl, alpha=1, beta=0, seed=17, select="prwm")
+    rng = np.random.default_rng(n + cl)
+    tau = rng.integers(1, 9, size=(n, n)).astype(np.float32)
+    col.set_pheromone(tau)
+    col.prepare_choice()
+    col.construct(4, nthreads=4)
+    cand = ref_candidates(d, cl) if cl else None
+    L = orc.lib()
+    bad = sequential_wheel_tours(col.tours(), tau, cand, lambda s, it, a, k: L.orc_draw_word(s, it, a, k, 0), 17, 4)
+    assert bad is None, f"ant {bad[0]} differs at step {bad[1]}"
+    if cl:
+        steps, _ = col.fallback()
+        assert steps.sum() > 0  # the fallback (two stages over > 64 cities) ran
