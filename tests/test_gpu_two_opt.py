@@ -81,3 +81,25 @@ def test_iterations_with_two_opt(gpu, tabu):
 def test_two_opt_dense_trails(gpu):
     _, d = I.make_instance("clustered", 300, seed=8, clusters=5, sigma=500.0)
     run_parity(d, 3, ants=30, cand_len=12, rho=0.1, seed=4, ls_nn=8)
+
+
+def test_search_order_worked_example(gpu):
+    """The hand-derived 6-city run of the search order (see
+    tests/test_oracle_two_opt.py): every ant starts from the same tour and
+    must end at the derived 2-optimal tour, in every launch shape."""
+    from paper_2003_11902_amd import mmas as M
+    from tests.test_oracle_two_opt import read_order_example
+    import torch
+    d, tour, expected, length = read_order_example()
+    for waves in (1, 4, 16):
+        say(f"2-opt worked example, waves {waves}")
+        g = M.Colony(d, 5, cand_len=5, rho=0.1, seed=1, pher="candidates", ls_nn=5)
+        g.set_two_opt_launch(waves)
+        g.construct(0)
+        t0 = np.tile(np.array(tour, dtype=np.uint16), (5, 1))
+        g.tensor(M.MMAS_BUF_TOURS).copy_(torch.from_numpy(t0.view(np.int16).ravel()).cuda())
+        g.synchronize()
+        g.two_opt()
+        assert (g.tours() == np.array(expected, dtype=np.uint16)).all()
+        assert (g.lengths() == length).all()
+        assert (g.state().flags & 16) == 0

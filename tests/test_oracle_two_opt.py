@@ -93,3 +93,69 @@ def test_mmas_finds_optimum_of_tiny_instances(orc, ls_nn):
         assert col.best()[1] >= opt
         hits += col.best()[1] == opt
     assert hits >= 19
+
+
+def read_order_example():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "two_opt_order6.txt")
+    rows, tour, expected, length = [], None, None, None
+    for line in open(path):
+        line = line.split("#")[0].split()
+        if not line:
+            continue
+        if line[0] == "tour":
+            tour = [int(x) for x in line[1:]]
+        elif line[0] == "expected":
+            expected = [int(x) for x in line[1:]]
+        elif line[0] == "length":
+            length = int(line[1])
+        else:
+            rows.append([int(x) for x in line])
+    return np.array(rows, dtype=np.int32), tour, expected, length
+
+
+def test_search_order_worked_example(orc):
+    """Reading 19 of Sec. 5.7's search order, pinned by a hand-derived run.
+
+    Neighbour lists by (d, index): 0: 1 4 2 3 5; 1: 0 2 4 3 5; 2: 1 0 4 3 5;
+    3: 4 0 5 1 2; 4: 3 0 1 2 5; 5: 3 4 0 1 2. Start tour T0 = [5 1 2 4 3 0]
+    (length 25+7+15+4+11+22 = 84).
+
+    City 0, successor a' = 5, d(0,5) = 22:
+      c = 1: g1 = 22-4 = 18, c' = succ(1) = 2, gain = 18 + d(1,2) - d(5,2)
+             = 18+7-31 = -6;
+      c = 4: g1 = 22-6 = 16, c' = succ(4) = 3, gain = 16+4-12 = 8 > 0: move.
+      The paths a'..c (positions 0-3, 4 cities) and c'..a (positions 4-5,
+      2 cities): the shorter one is reversed, T1 = [5 1 2 4 0 3] (76).
+    City 0 again, a' = succ(0) = 3, d(0,3) = 11:
+      c = 1: g1 = 7, c' = 2, gain = 7+7-19 = -5;
+      c = 4: g1 = 5, c' = succ(4) = 0 = a: skipped;
+      c = 2: g1 = 1, c' = succ(2) = 4, gain = 1+15-4 = 12 > 0: move.
+      Paths a'..c (positions 5,0,1,2: 4 cities) and c'..a (positions 3-4):
+      the latter is reversed, T2 = [5 1 2 0 4 3] (64).
+    City 0 again: successor 4 (d 6): c = 1: g1 = 2, gain = 2+7-15 = -6;
+      c = 4: g1 = 0, stop. Predecessor 2 (d 10): c = 1: g1 = 6, c' =
+      pred(1) = 5, gain = 6+25-31 = 0 (not positive); c = 4: c' = pred(4) =
+      0 = a, skipped; c = 2: g1 = 0, stop. Its bit is set.
+    Cities 1-5 then find no improving move either: T2 is 2-optimal (checked
+    below by brute force), so the search ends with T2.
+
+    Each alternative reading ends elsewhere (as a tour, not only as an
+    array): predecessor first moves at city 0 with c = 1 (g1 = 11-4 = 7,
+    c' = pred(1) = 5, gain = 7+25-12 = 20) and ends at [0 1 2 4 3 5];
+    leaving city 0 after its first move ends at [3 4 2 1 0 5]; reversing the
+    longer path first gives [4 2 1 5 3 0] and ends at [1 0 4 5 3 2]. All
+    three have a different edge set from T2."""
+    d, tour, expected, length = read_order_example()
+    nn = orc.nearest(d, 5)
+    assert nn.tolist() == [[1, 4, 2, 3, 5], [0, 2, 4, 3, 5], [1, 0, 4, 3, 5], [4, 0, 5, 1, 2], [3, 0, 1, 2, 5],
+                           [3, 4, 0, 1, 2]]
+    assert orc.tour_length(d, np.array(tour)) == 84
+    t, L = orc.two_opt_tour(d, nn, np.array(tour))
+    assert t.tolist() == expected and L == length == orc.tour_length(d, np.array(expected))
+    assert improving_2opt_moves(d, expected) == []
+
+    def edges(x):
+        return {frozenset((x[i], x[(i + 1) % len(x)])) for i in range(len(x))}
+    for other in ([0, 1, 2, 4, 3, 5], [3, 4, 2, 1, 0, 5], [1, 0, 4, 5, 3, 2]):
+        assert edges(other) != edges(expected)
