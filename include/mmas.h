@@ -320,6 +320,17 @@ mmas_status mmas_batch_capture(mmas_batch* b);
 /* One iteration for every instance (graph replay if captured). */
 mmas_status mmas_batch_step(mmas_batch* b);
 
+/* Per-launch timing of the batched construction: with `on` != 0 every later
+ * step runs its launches directly (a captured graph is kept but not replayed
+ * meanwhile; the kernels and their launch shape are the graph's) and a
+ * hipEvent pair brackets the construction launch on the batch's stream. Off
+ * by default; turning it off keeps what was gathered. */
+mmas_status mmas_batch_set_timing(mmas_batch* b, int32_t on);
+
+/* Milliseconds and launch count of the timed constructions (either pointer
+ * may be NULL); `reset` != 0 clears them afterwards. Synchronises. */
+mmas_status mmas_batch_read_timing(mmas_batch* b, double* construct_ms, int64_t* calls, int32_t reset);
+
 /* Number of completed steps (synchronises). */
 mmas_status mmas_batch_iteration(mmas_batch* b, uint32_t* iteration);
 

@@ -20,6 +20,16 @@ PHER_CANDIDATES = 1
 _lib = None
 
 
+def use_library(path: str):
+    """Load the oracle from another build of the same sources (e.g. the
+    -march=native build of build.build(native=True)) for the rest of the
+    process; call before the first use."""
+    global _lib, LIB_PATH
+    if _lib is not None and LIB_PATH != path:
+        raise RuntimeError("the oracle library is already loaded")
+    LIB_PATH = path
+
+
 def lib():
     global _lib
     if _lib is None:

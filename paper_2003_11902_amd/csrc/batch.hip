@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <new>
 #include <numeric>
+#include <utility>
 #include <vector>
 
 #include "internal.hpp"
@@ -45,6 +46,12 @@ struct mmas_batch {
     std::vector<mmas::BatchTile> tiles;
     hipGraph_t graph;
     hipGraphExec_t exec;
+    // per-launch timing of the construction (mmas_batch_set_timing): event
+    // pairs not yet read, spare pairs, and the totals
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending, spare;
+    double construct_ms = 0.0;
+    int64_t construct_calls = 0;
 };
 
 namespace {
@@ -96,9 +103,29 @@ mmas_status rebuild_tiles(mmas_batch* b) {
 }
 
 mmas_status launch_step(mmas_batch* b) {
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (b->timing) {
+        if (!b->spare.empty()) {
+            ev = b->spare.back();
+            b->spare.pop_back();
+        } else {
+            hipError_t ce = hipEventCreate(&ev.first);
+            if (ce == hipSuccess) ce = hipEventCreate(&ev.second);
+            if (ce != hipSuccess) return mmas::hip_fail(ce, "timing events");
+        }
+        const hipError_t re = hipEventRecord(ev.first, b->stream);
+        if (re != hipSuccess) return mmas::hip_fail(re, "timing event record");
+    }
     hipError_t e = mmas::launch_batch_construct(b->d_items, b->d_tiles, b->ntiles, b->d_queue, b->d_it, b->tabu,
                                                 b->pher, b->ants_per_block, b->lanes_per_ant, b->table_bytes,
                                                 b->per_ant, b->grid, b->stream);
+    if (b->timing) {
+        if (e == hipSuccess) e = hipEventRecord(ev.second, b->stream);
+        if (e == hipSuccess)
+            b->pending.push_back(ev);
+        else
+            b->spare.push_back(ev);
+    }
     if (e != hipSuccess) return mmas::hip_fail(e, "batched construction launch");
     e = mmas::launch_batch_update(b->d_items, b->count, b->d_row_start, b->total_rows, b->d_it, b->d_queue, b->stream);
     return e == hipSuccess ? MMAS_OK : mmas::hip_fail(e, "batched update launch");
@@ -110,6 +137,25 @@ void apply_tabu(mmas_batch* b, int tabu) {
     b->tabu = tabu;
     b->per_ant = b->per_ant_tabu[tabu];
     for (auto& it : b->items) it.s.tabu = tabu;
+}
+
+// Adds up the timed launches that have finished (waits for them).
+hipError_t fold_timing(mmas_batch* b) {
+    hipError_t first = hipSuccess;
+    for (auto& ev : b->pending) {
+        hipError_t e = hipEventSynchronize(ev.second);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev.first, ev.second);
+        if (e == hipSuccess) {
+            b->construct_ms += ms;
+            b->construct_calls += 1;
+        } else if (first == hipSuccess) {
+            first = e;
+        }
+        b->spare.push_back(ev);
+    }
+    b->pending.clear();
+    return first;
 }
 
 void drop_graph(mmas_batch* b) {
@@ -340,7 +386,7 @@ mmas_status mmas_batch_capture(mmas_batch* b) {
 
 mmas_status mmas_batch_step(mmas_batch* b) {
     if (!b) return MMAS_EINVAL;
-    if (b->exec) {
+    if (b->exec && !b->timing) {
         const hipError_t e = hipGraphLaunch(b->exec, b->stream);
         return e == hipSuccess ? MMAS_OK : mmas::hip_fail(e, "graph launch");
     }
@@ -360,11 +406,34 @@ mmas_status mmas_batch_context(mmas_batch* b, int32_t index, mmas_ctx** ctx) {
     return MMAS_OK;
 }
 
+mmas_status mmas_batch_set_timing(mmas_batch* b, int32_t on) {
+    if (!b) return MMAS_EINVAL;
+    b->timing = on != 0;
+    return MMAS_OK;
+}
+
+mmas_status mmas_batch_read_timing(mmas_batch* b, double* construct_ms, int64_t* calls, int32_t reset) {
+    if (!b) return MMAS_EINVAL;
+    const hipError_t e = fold_timing(b);
+    if (construct_ms) *construct_ms = b->construct_ms;
+    if (calls) *calls = b->construct_calls;
+    if (reset) {
+        b->construct_ms = 0.0;
+        b->construct_calls = 0;
+    }
+    return e == hipSuccess ? MMAS_OK : mmas::hip_fail(e, "timing read");
+}
+
 void mmas_batch_destroy(mmas_batch* b) {
     if (!b) return;
     // the caller may free the workspace right after this call: let every
     // step already enqueued (a graph replay included) finish first
     (void)hipStreamSynchronize(b->stream);
+    for (auto& ev : b->pending) b->spare.push_back(ev);
+    for (auto& ev : b->spare) {
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
     drop_graph(b);
     for (mmas_ctx* c : b->ctx) mmas_destroy(c);
     delete b;

@@ -47,8 +47,10 @@ def init_params(seed: int, bias: float = 0.0) -> np.ndarray:
 
 
 def training_set(count=2000, n_lo=200, n_hi=1000, base_seed=20000, R=4, iterations=100, ants=64, cand_len=32,
-                 rho=0.02, log=print):
-    """(X uint16 [E,16] bfloat16 bits, targets float32 [E]) on the GPU."""
+                 rho=0.02, colonies_per_batch=2048, log=print):
+    """(X uint16 [E,16] bfloat16 bits, targets float32 [E]) on the GPU. The
+    colonies (instances x R seeds) are solved in batches of about
+    `colonies_per_batch`, so that each batched step keeps the GPU busy."""
     import torch
 
     rng = np.random.default_rng(base_seed)
@@ -61,7 +63,7 @@ def training_set(count=2000, n_lo=200, n_hi=1000, base_seed=20000, R=4, iteratio
         insts.append((xy, d))
     log(f"[learned] {count} instances generated in {time.perf_counter() - t0:.1f} s")
     Xs, Fs = [], []
-    chunk = max(1, 256 // R)  # instances per batch
+    chunk = max(1, colonies_per_batch // R)  # instances per batch
     for c0 in range(0, count, chunk):
         part = insts[c0:c0 + chunk]
         dists, params = [], []
@@ -70,6 +72,7 @@ def training_set(count=2000, n_lo=200, n_hi=1000, base_seed=20000, R=4, iteratio
                 dists.append(d)
                 params.append(M.make_params(d.shape[0], ants, cand_len=cand_len, rho=rho, seed=1 + r))
         b = M.Batch(dists, params)
+        b.capture()
         for _ in range(iterations):
             b.step()
         b.synchronize()

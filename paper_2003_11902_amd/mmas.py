@@ -60,7 +60,7 @@ EXPORTED = (
     "mmas_batch_destroy", "mmas_mlp_param_count", "mmas_mlp_packed_count", "mmas_mlp_features",
     "mmas_mlp_pack", "mmas_mlp_forward", "mmas_mlp_grad", "mmas_mlp_adam", "mmas_mlp_labels",
     "mmas_set_learned_heuristic", "mmas_last_error", "mmas_set_two_opt_launch", "mmas_batch_set_tabu",
-    "mmas_restore", "mmas_set_timing", "mmas_read_timing",
+    "mmas_restore", "mmas_set_timing", "mmas_read_timing", "mmas_batch_set_timing", "mmas_batch_read_timing",
 )
 
 
@@ -155,6 +155,10 @@ def _load():
         getattr(L, name).restype = C.c_int
     L.mmas_batch_iteration.argtypes = [p, C.POINTER(C.c_uint32)]
     L.mmas_batch_iteration.restype = C.c_int
+    L.mmas_batch_set_timing.argtypes = [p, C.c_int32]
+    L.mmas_batch_set_timing.restype = C.c_int
+    L.mmas_batch_read_timing.argtypes = [p, p, p, C.c_int32]
+    L.mmas_batch_read_timing.restype = C.c_int
     L.mmas_batch_context.argtypes = [p, C.c_int32, C.POINTER(p)]
     L.mmas_batch_context.restype = C.c_int
     L.mmas_batch_destroy.argtypes = [p]
@@ -531,6 +535,17 @@ class Batch:
 
     def synchronize(self):
         self.stream.synchronize()
+
+    def set_timing(self, on=True):
+        _check(lib.mmas_batch_set_timing(self._h, 1 if on else 0), "mmas_batch_set_timing")
+
+    def read_timing(self, reset=False):
+        """(milliseconds, launches) of the timed constructions."""
+        ms = C.c_double()
+        calls = C.c_int64()
+        _check(lib.mmas_batch_read_timing(self._h, C.byref(ms), C.byref(calls), 1 if reset else 0),
+               "mmas_batch_read_timing")
+        return float(ms.value), int(calls.value)
 
     def instance(self, i) -> Colony:
         h = C.c_void_p()

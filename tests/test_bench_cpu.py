@@ -49,3 +49,29 @@ def test_traffic_record_guard(bench):
 
 def test_cpu_model_is_text(bench):
     assert isinstance(bench.cpu_model(), str) and bench.cpu_model()
+
+
+def test_native_oracle_build_gives_the_same_results(tmp_path):
+    """The CPU baseline times the oracle built with -march=native; with
+    contraction off it must compute exactly what the portable build does."""
+    from oracle import build as OB
+    native = OB.build(native=True)
+    prog = (
+        "import sys, numpy as np\n"
+        f"sys.path.insert(0, {ROOT!r})\n"
+        "from oracle import oracle as O\n"
+        "if sys.argv[1] != '-': O.use_library(sys.argv[1])\n"
+        "from paper_2003_11902_amd import instances as I\n"
+        "_, d = I.make_instance('clustered', 300, seed=5, clusters=6, sigma=400.0)\n"
+        "o = O.Colony(d, 60, cand_len=16, rho=0.05, seed=3)\n"
+        "for it in range(3): o.iterate(it, 2)\n"
+        "np.save(sys.argv[2], np.concatenate([o.tours().ravel().astype(np.int64), o.lengths(),\n"
+        "        o.pheromone().view(np.uint32).ravel().astype(np.int64)]))\n")
+    outs = []
+    for lib, name in ((native, "native.npy"), ("-", "portable.npy")):
+        r = subprocess.run([sys.executable, "-c", prog, lib, str(tmp_path / name)], capture_output=True, text=True,
+                           timeout=300)
+        assert r.returncode == 0, r.stderr
+        import numpy as np
+        outs.append(np.load(tmp_path / name))
+    assert (outs[0] == outs[1]).all()
