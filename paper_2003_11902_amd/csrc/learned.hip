@@ -83,6 +83,13 @@ __device__ __forceinline__ float gelu_d(float z) {
 
 // ---- features ----------------------------------------------------------------
 
+// in-degree counters cleared by a kernel rather than a memset node, so that
+// the feature pass can be captured into a graph and replayed
+__global__ __launch_bounds__(256) void k_zero_i32(int* __restrict__ a, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) a[i] = 0;
+}
+
 __global__ __launch_bounds__(256) void k_feat_city(const int32_t* __restrict__ dist, const uint16_t* __restrict__ knn,
                                                    int n, float* __restrict__ dbar, int* __restrict__ indeg) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -504,7 +511,8 @@ int mlp_packed_count() { return kPacked; }
 
 hipError_t launch_features(const int32_t* dist, const float* xy, const uint16_t* knn, int n, float* dbar, int* indeg,
                            float* feat, uint16_t* X, hipStream_t st) {
-    hipError_t e = hipMemsetAsync(indeg, 0, sizeof(int) * (size_t)n, st);
+    k_zero_i32<<<(n + 255) / 256, 256, 0, st>>>(indeg, n);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_feat_city<<<(n + 255) / 256, 256, 0, st>>>(dist, knn, n, dbar, indeg);
     if ((e = hipGetLastError()) != hipSuccess) return e;
