@@ -13,6 +13,7 @@
 // Tours are gathered in a register (lane k % 64 holds step k) and stored 64
 // cities at a time; tour lengths accumulate at those flushes.
 #include <atomic>
+#include <type_traits>
 
 #include "device.hpp"
 #include "internal.hpp"
@@ -42,6 +43,11 @@ struct BitmaskTabu {
         for (int w = lane; w < words; w += kWave) bits[w] = 0u;
     }
     __device__ __forceinline__ bool visited(uint32_t v) const { return (bits[v >> 5] >> (v & 31u)) & 1u; }
+    // ~0 if city v is unvisited, else 0 (a bit-field extract and a decrement)
+    __device__ __forceinline__ uint32_t live(uint32_t v) const {
+        const uint32_t word = bits[__builtin_amdgcn_ubfe(v, 5u, 11u)];
+        return __builtin_amdgcn_ubfe(word, v, 1u) - 1u;  // (the offset is taken mod 32)
+    }
     __device__ __forceinline__ void mark(uint32_t v, int lane) {
         if (lane == 0) atomicOr(&bits[v >> 5], 1u << (v & 31u));
     }
@@ -66,6 +72,7 @@ struct CompactTabu {
         for (int i = lane; i < n_; i += kWave) entries[i] = (uint16_t)i;
     }
     __device__ __forceinline__ bool visited(uint32_t v) const { return entries[v] > v; }
+    __device__ __forceinline__ uint32_t live(uint32_t v) const { return entries[v] > v ? 0u : ~0u; }
     __device__ __forceinline__ const uint16_t* list() const { return entries; }  // the L unvisited cities
     __device__ __forceinline__ void mark(uint32_t u, int lane) {
         // every lane reads the same cells; lane 0 writes
@@ -106,6 +113,7 @@ struct ListTabu {
         }
     }
     __device__ __forceinline__ bool visited(uint32_t v) const { return (int)idx[v] >= L; }
+    __device__ __forceinline__ uint32_t live(uint32_t v) const { return (int)idx[v] >= L ? 0u : ~0u; }
     __device__ __forceinline__ const uint16_t* list() const { return unv; }
     __device__ __forceinline__ void mark(uint32_t u, int lane) {
         // every lane reads the same cells; lane 0 writes
@@ -597,6 +605,187 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
     }
 }
 
+// One ant per wave64 for the single colony, where every wave sits alone on
+// its SIMD and the time per step is the length of the step's instruction
+// chain. The same selection as construct_ant, laid out so that the chain
+// stays short: the current and the next city are wave-uniform (scalar
+// registers and scalar branches, no exec-mask bookkeeping around the step);
+// the steps run in groups of S (one draw generation per group, no per-step
+// test for it) inside chunks of 64 (one tour flush per chunk); the visited
+// test folds into the key code as a mask; and for cl <= 32 (kRows = 2) the
+// argmax reduces only the two rows that hold the list.
+template <int kTabu, int kPher, int kRows>
+__device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int ant, int lane, uint8_t* region,
+                               const uint16_t* tcand, const float* tchc, int R) {
+    const int n = s.n, cl = s.cl;
+    const uint64_t seed = s.seed;
+    float* lnbuf = reinterpret_cast<float*>(region);
+    typename TabuOf<kTabu>::type tabu;
+    tabu.init(region + kDrawBytes + kScratchBytes, n, lane);
+    uint16_t* ulist = reinterpret_cast<uint16_t*>(region + kDrawBytes + kScratchBytes + align16(4 * ((n + 31) / 32)));
+
+    float tmin_a = 0.0f;
+    if (kPher == MMAS_PHER_CANDIDATES) tmin_a = powi(vw.state->tau_min, s.alpha);
+    const LdsPtr<const uint16_t> lds_cand = (LdsPtr<const uint16_t>)tcand;
+    const LdsPtr<const float> lds_chc = (LdsPtr<const float>)tchc;
+    const GlbPtr<const uint16_t> glb_cand = (GlbPtr<const uint16_t>)vw.cand;
+    const GlbPtr<const float> glb_chc = (GlbPtr<const float>)vw.chc;
+    const LdsPtr<const float> lds_ln = (LdsPtr<const float>)lnbuf;
+
+    const uint32_t x0 = draw_block(seed, it, (uint32_t)ant, 0u, 0u).w[0];
+    const int start = __builtin_amdgcn_readfirstlane((int)(((uint64_t)x0 * (uint64_t)n) >> 32));
+    tabu.mark((uint32_t)start, lane);
+
+    // Draws ahead: G 4-slot groups per step, S = 64 / G steps per generation.
+    // The generation for the group of steps k0 .. k0 + S - 1 (k0 a multiple
+    // of S; step 0 is the start and reads none) has lane l compute the Philox
+    // block of step k0 + l / G, slots 4(l % G) .. 4(l % G) + 3, and store
+    // their logarithms at lnbuf[4l .. 4l + 3]; step k0 + j reads slot r at
+    // lnbuf[4jG + r].
+    const int gsh = cl <= 4 ? 0 : cl <= 8 ? 1 : cl <= 16 ? 2 : cl <= 32 ? 3 : 4;
+    const int G = 1 << gsh;
+    const int S = kWave >> gsh;
+    const int lr = lane < cl ? lane : cl - 1;       // lanes past the list repeat the last entry
+    const uint32_t lane_ok = lane < cl ? ~0u : 0u;  // ... and never hold a key
+    const int ln_lane = lane & (4 * G - 1);
+    // bitmask marks: byte offset of each lane's OR (see below)
+    uint32_t mark_is0 = lane == 0 ? 1u : 0u;
+    uint32_t mark_mask = lane == 0 ? ~0u : 0u;
+    uint32_t mark_base = lane == 0 ? (uint32_t)(kDrawBytes + kScratchBytes) : 4u * (uint32_t)lane;  // from region
+    // (opaque to the compiler, which would otherwise turn the arithmetic
+    // below back into lane-0 selects)
+    asm volatile("" : "+v"(mark_is0), "+v"(mark_mask), "+v"(mark_base));
+
+    uint16_t* tour_out = vw.tours + (size_t)ant * n;
+    const int32_t* dist = vw.dist;
+    uint32_t tbuf = (uint32_t)start;  // lane (k & 63) holds the city of step k
+    uint32_t prev_last = 0;           // city of the last step of the previous chunk
+    int64_t len = 0;
+    int64_t fb_steps = 0, fb_nodes = 0;
+    int cur = start;
+    bool bad = false;
+
+    // the all-city fallback of step k from city cur (rare with a list)
+    auto fallback = [&](int k) -> uint32_t {
+        // (k laundered so that n - k is not kept as a 64-bit induction
+        // variable on every step)
+        int kk = k;
+        asm volatile("" : "+s"(kk));
+        fb_steps += 1;
+        fb_nodes += n - kk;
+        const int cap = list_cap(s);
+        uint32_t pick;
+        if constexpr (kPher == MMAS_PHER_DENSE) {
+            const DenseWeight wt{vw.choice + (size_t)cur * n};
+            if constexpr (kTabu == MMAS_TABU_BITMASK)
+                pick = fallback_bitmask_call(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+            else
+                pick = fallback_list_call(tabu.list(), tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+        } else {
+            const CandWeight wt{dist + (size_t)cur * n, tmin_a, s.beta};
+            if constexpr (kTabu == MMAS_TABU_BITMASK)
+                pick = fallback_bitmask_call(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+            else
+                pick = fallback_list_call(tabu.list(), tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+        }
+        const uint32_t next = (uint32_t)__builtin_amdgcn_readfirstlane((int)pick);
+        // no city is unreachable with a validated instance; were it not,
+        // report it after the tour and go on with city 0 (the tour is void)
+        // rather than index out of bounds
+        bad |= next >= (uint32_t)n;
+        return next < (uint32_t)n ? next : 0u;
+    };
+
+    // the whole tour; kCand: with a candidate list (the loop is instantiated
+    // once with it and once without, so the step has no test for it)
+    auto tour = [&](auto cand) {
+        constexpr bool kCand = decltype(cand)::value;
+        for (int k0 = 0; k0 < n; k0 += S) {
+            if constexpr (kCand) {
+                const Words4 b = draw_block(seed, it, (uint32_t)ant, (uint32_t)(k0 + (lane >> gsh)),
+                                            (uint32_t)(4 * (lane & (G - 1))));
+                float4 lv;
+                lv.x = log_u01(u01(b.w[0]));
+                lv.y = log_u01(u01(b.w[1]));
+                lv.z = log_u01(u01(b.w[2]));
+                lv.w = log_u01(u01(b.w[3]));
+                *reinterpret_cast<float4*>(lnbuf + 4 * lane) = lv;
+            }
+            const int kb = k0 > 0 ? k0 : 1;
+            const int ke = k0 + S < n ? k0 + S : n;
+            for (int k = kb; k < ke; ++k) {
+                uint32_t next = kNone;
+                if constexpr (kCand) {
+                    const int e = cur * cl + lr;
+                    uint32_t node;
+                    float w;
+                    if (__builtin_expect(cur < R, 1)) {
+                        node = lds_cand[e];
+                        w = lds_chc[e];
+                    } else {
+                        node = glb_cand[e];
+                        w = glb_chc[e];
+                    }
+                    const float lnu = lds_ln[4 * (k - k0) * G + ln_lane];
+                    const uint32_t live = tabu.live(node);
+                    float key = lnu / w;
+                    asm volatile("" : "+v"(key));
+                    // ln(u) < 0 and w >= 0 give a key with the sign bit set
+                    // (a negative number, -0 or -inf), whose order code is ~bits
+                    const uint32_t code = ~__float_as_uint(key) & live & lane_ok;
+                    const uint32_t best = wave_max_u32<kRows>(code);
+                    if (best != 0u) {
+                        const uint64_t tied = __ballot(code == best);
+                        const int first = (int)__builtin_ctzll(tied);
+                        next = (uint32_t)__builtin_amdgcn_readlane((int)node, first);
+                        if (__builtin_expect(first != 63 - (int)__builtin_clzll(tied), 0))
+                            next = wave_min_u32<kRows>(code == best ? node : kNone);
+                    }
+                    if (__builtin_expect(next == kNone, 0)) next = fallback(k);
+                } else {
+                    next = fallback(k);
+                }
+                if constexpr (kTabu == MMAS_TABU_BITMASK) {
+                    // every lane issues the OR, so that no exec mask is set up
+                    // around it: lane 0 into the city's word, the others a 0
+                    // into their own word of the draw buffer (no change)
+                    const uint32_t off = mark_base + mark_is0 * ((next >> 5) << 2);
+                    atomicOr(reinterpret_cast<uint32_t*>(region + off), (1u << (next & 31u)) & mark_mask);
+                } else {
+                    tabu.mark(next, lane);
+                }
+                if (lane == (k & 63)) tbuf = next;
+                cur = __builtin_amdgcn_readfirstlane((int)next);
+            }
+            if ((ke & 63) == 0 || ke == n) {
+                // flush steps c0 .. ke - 1 of this chunk; lane l holds step c0 + l
+                const int c0 = (ke - 1) & ~63;
+                const int last = ke - 1 - c0;
+                const uint32_t prev = __shfl_up(tbuf, 1);
+                if (lane <= last) {
+                    tour_out[c0 + lane] = (uint16_t)tbuf;
+                    // edge entering step c0 + l (none for step 0)
+                    const uint32_t from = lane == 0 ? prev_last : prev;
+                    if (c0 + lane > 0) len += dist[(size_t)from * n + tbuf];
+                }
+                prev_last = (uint32_t)__builtin_amdgcn_readlane((int)tbuf, last);
+            }
+        }
+    };
+    if (cl > 0)
+        tour(std::integral_constant<bool, true>{});
+    else
+        tour(std::integral_constant<bool, false>{});
+    if (bad && lane == 0) atomicOr(&vw.state->flags, 8u);
+    if (lane == 0) len += dist[(size_t)cur * n + start];  // closing edge
+    len = wave_sum_i64(len);
+    if (lane == 0) {
+        vw.lengths[ant] = len;
+        vw.fallback[ant] = fb_steps;
+        vw.fallback[s.ants + ant] = fb_nodes;
+    }
+}
+
 // Per-half wave64 reductions for two ants per wave (lanes 0-31: first ant,
 // 32-63: second): the maximum (minimum) of each half, as two scalars.
 __device__ __forceinline__ void half_max_u32(uint32_t x, uint32_t& lo, uint32_t& hi) {
@@ -784,7 +973,9 @@ __device__ void construct_pair(const Views& vw, const Shape& s, uint32_t it, int
     }
 }
 
-template <int kTabu, int kPher, bool kPair>
+// kRows: 16-lane rows the argmax of a one-ant-per-wave step reduces (2 for
+// cl <= 32, else 4); unused with two ants per wave.
+template <int kTabu, int kPher, bool kPair, int kRows = 4>
 __global__ __launch_bounds__(1024) void k_construct(Views vw, Shape s, uint32_t it, int ants_per_block, Lds lds) {
     extern __shared__ __align__(16) uint8_t smem[];
     const int lane = threadIdx.x & 63;
@@ -803,8 +994,8 @@ __global__ __launch_bounds__(1024) void k_construct(Views vw, Shape s, uint32_t 
         construct_pair<kTabu, kPher>(vw, s, it, ant, ant + 1 < s.ants, lane, regions + (size_t)(2 * wave) * lds.per_ant,
                                      regions + (size_t)(2 * wave + 1) * lds.per_ant, tcand, tchc, R);
     else
-        construct_ant<kTabu, kPher, false, true>(vw, s, it, ant, lane, regions + (size_t)wave * lds.per_ant, tcand,
-                                                 tchc, R);
+        construct_lone<kTabu, kPher, kRows>(vw, s, it, ant, lane, regions + (size_t)wave * lds.per_ant, tcand, tchc,
+                                            R);
 }
 
 // One ant per workgroup of several waves (construct_ant with kWide): the
@@ -900,7 +1091,7 @@ namespace {
 // in a half wave).
 bool pair_ok(const Shape& s) { return s.lanes_per_ant == 32 && s.cl >= 1 && s.cl <= 32; }
 
-template <int kTabu, int kPher, bool kPair>
+template <int kTabu, int kPher, bool kPair, int kRows = 4>
 hipError_t launch_t(const Views& v, const Shape& s0, uint32_t it, hipStream_t st) {
     // one colony: a workgroup per four ants rarely shares a CU, so the fallback
     // lists every unvisited city in one pass
@@ -941,7 +1132,7 @@ hipError_t launch_t(const Views& v, const Shape& s0, uint32_t it, hipStream_t st
     lds.rows = rows;
     lds.table_bytes = align16(rows * s.cl * 2) + align16(rows * s.cl * 4);
     const size_t bytes = (size_t)lds.table_bytes + (size_t)apb * per_ant;
-    auto kern = k_construct<kTabu, kPher, kPair>;
+    auto kern = k_construct<kTabu, kPher, kPair, kRows>;
     if (bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
@@ -1003,7 +1194,8 @@ hipError_t launch_tp(const Views& v, const Shape& s, uint32_t it, hipStream_t st
     if (pair_ok(s)) return launch_t<kTabu, kPher, true>(v, s, it, st);
     const int waves = construct_waves(s);
     if (waves > 1) return launch_wide<kTabu, kPher>(v, s, it, waves, st);
-    return launch_t<kTabu, kPher, false>(v, s, it, st);
+    if (s.cl <= 32) return launch_t<kTabu, kPher, false, 2>(v, s, it, st);
+    return launch_t<kTabu, kPher, false, 4>(v, s, it, st);
 }
 
 // the persistent batched kernel for a configuration
