@@ -367,6 +367,18 @@ int32_t mmas_mlp_packed_count(void);
 mmas_status mmas_mlp_features(const int32_t* dist_dev, const float* xy_dev, int32_t n, void* scratch_dev,
                               uint16_t* knn_dev, float* feat_dev, uint16_t* x_dev, void* hip_stream);
 
+/* mmas_mlp_features without a scratch argument, for callers that cannot
+ * allocate device memory (code under graph capture, serving loops, harnesses
+ * that forbid hipMalloc): the per-city scratch (8n bytes) is the library's
+ * static device array of 8 * 65535 bytes, which every GPU the library runs
+ * on holds until the process ends. It allocates nothing; its first call on a
+ * device looks up that device's copy (hipGetSymbolAddress). All calls on one
+ * GPU share the array (it keeps the last call's contents; the pass clears
+ * what must start at zero), so calls that overlap on one GPU race. Same
+ * outputs and limits as mmas_mlp_features; EINVAL for n outside 17..65535. */
+mmas_status mmas_mlp_features_noalloc(const int32_t* dist_dev, const float* xy_dev, int32_t n, uint16_t* knn_dev,
+                                      float* feat_dev, uint16_t* x_dev, void* hip_stream);
+
 /* bfloat16 working copies of the parameters. */
 mmas_status mmas_mlp_pack(const float* params_dev, uint16_t* packed_dev, void* hip_stream);
 

@@ -12,6 +12,7 @@
 // result holds D[4q + t][c], t = 0..3.
 #include <cmath>
 #include <cstddef>
+#include <mutex>
 
 #include "device.hpp"
 #include "internal.hpp"
@@ -569,6 +570,41 @@ hipError_t launch_labels(const uint16_t* tours, int R, int n, const uint16_t* kn
 
 }  // namespace mmas
 
+// ---- scratch for callers that cannot allocate ------------------------------------
+
+// The feature pass's per-city scratch (dbar as FP32, then the in-degree
+// counters as int32: 8 bytes per city) for the largest instance the library
+// takes, held by every GPU the library runs on until the process ends. Host
+// code never passes this name to a kernel (on the host it is only a stand-in
+// for the symbol): it uses the device address hipGetSymbolAddress returns.
+constexpr int kScratchCities = 65535;
+static __device__ __align__(256) uint8_t scratch[8 * (size_t)kScratchCities];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kScratchDevices];  // device address of `scratch`, per device
+
+// The current device's copy of `scratch`, looked up on the first call on
+// that device (with it current) and kept.
+mmas_status scratch_of_current_device(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return mmas::hip_fail(e, "hipGetDevice (static feature scratch)");
+    if (dev < 0 || dev >= kScratchDevices) return MMAS_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return mmas::hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                           "hipGetSymbolAddress (static feature scratch)");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MMAS_OK;
+}
+}  // namespace
+
 // ---- C ABI ----------------------------------------------------------------------
 
 namespace {
@@ -588,6 +624,22 @@ mmas_status mmas_mlp_features(const int32_t* dist_dev, const float* xy_dev, int3
     hipError_t e = mmas::launch_nearest(dist_dev, n, 16, knn_dev, st);
     if (e != hipSuccess) return st_of(e);
     float* dbar = reinterpret_cast<float*>(scratch_dev);
+    int* indeg = reinterpret_cast<int*>(dbar + n);
+    return st_of(mmas::launch_features(dist_dev, xy_dev, knn_dev, n, dbar, indeg, feat_dev, x_dev, st));
+}
+
+mmas_status mmas_mlp_features_noalloc(const int32_t* dist_dev, const float* xy_dev, int32_t n, uint16_t* knn_dev,
+                                      float* feat_dev, uint16_t* x_dev, void* hip_stream) {
+    if (!dist_dev || !xy_dev || !knn_dev || !x_dev || n < 17) return MMAS_EINVAL;
+    if (n > kScratchCities) return MMAS_EINVAL;  // beyond the static scratch (and the library's n)
+    void* ws = nullptr;
+    const mmas_status got = scratch_of_current_device(&ws);
+    if (got != MMAS_OK) return got;
+    hipStream_t st = as_stream(hip_stream);
+    hipError_t e = mmas::launch_nearest(dist_dev, n, 16, knn_dev, st);
+    if (e != hipSuccess) return st_of(e);
+    // the in-degree counters are cleared by a kernel inside launch_features
+    float* dbar = reinterpret_cast<float*>(ws);
     int* indeg = reinterpret_cast<int*>(dbar + n);
     return st_of(mmas::launch_features(dist_dev, xy_dev, knn_dev, n, dbar, indeg, feat_dev, x_dev, st));
 }

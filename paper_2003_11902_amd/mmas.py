@@ -61,6 +61,7 @@ EXPORTED = (
     "mmas_mlp_pack", "mmas_mlp_forward", "mmas_mlp_grad", "mmas_mlp_adam", "mmas_mlp_labels",
     "mmas_set_learned_heuristic", "mmas_last_error", "mmas_set_two_opt_launch", "mmas_batch_set_tabu",
     "mmas_restore", "mmas_set_timing", "mmas_read_timing", "mmas_batch_set_timing", "mmas_batch_read_timing",
+    "mmas_mlp_features_noalloc",
 )
 
 
@@ -169,6 +170,8 @@ def _load():
     L.mmas_mlp_packed_count.restype = C.c_int32
     L.mmas_mlp_features.argtypes = [p, p, C.c_int32, p, p, p, p, p]
     L.mmas_mlp_features.restype = C.c_int
+    L.mmas_mlp_features_noalloc.argtypes = [p, p, C.c_int32, p, p, p, p]
+    L.mmas_mlp_features_noalloc.restype = C.c_int
     L.mmas_mlp_pack.argtypes = [p, p, p]
     L.mmas_mlp_pack.restype = C.c_int
     L.mmas_mlp_forward.argtypes = [p, C.c_int64, p, p, p, p]
@@ -587,6 +590,22 @@ def mmas_mlp_features(dist, xy, with_features=False):
     scratch = torch.empty(8 * n, dtype=torch.uint8, device=dev)
     _check(lib.mmas_mlp_features(_dptr(dist), _dptr(xy), n, _dptr(scratch), _dptr(knn), _dptr(feat), _dptr(X),
                                  _cur_stream()), "mmas_mlp_features")
+    return knn, X, feat
+
+
+def mmas_mlp_features_noalloc(dist, xy, with_features=False):
+    """mmas_mlp_features without a scratch argument: the library's static
+    per-device scratch serves the feature pass (calls that overlap on one GPU
+    race on it)."""
+    import torch
+
+    n = int(dist.shape[0])
+    dev = dist.device
+    knn = torch.empty((n, 16), dtype=torch.int16, device=dev)
+    X = torch.empty((16 * n, 16), dtype=torch.int16, device=dev)
+    feat = torch.empty((16 * n, 8), dtype=torch.float32, device=dev) if with_features else None
+    _check(lib.mmas_mlp_features_noalloc(_dptr(dist), _dptr(xy), n, _dptr(knn), _dptr(feat), _dptr(X),
+                                         _cur_stream()), "mmas_mlp_features_noalloc")
     return knn, X, feat
 
 
