@@ -614,7 +614,7 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
 // test for it) inside chunks of 64 (one tour flush per chunk); the visited
 // test folds into the key code as a mask; and for cl <= 32 (kRows = 2) the
 // argmax reduces only the two rows that hold the list.
-template <int kTabu, int kPher, int kRows>
+template <int kTabu, int kPher, int kRows, int kG>
 __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int ant, int lane, uint8_t* region,
                                const uint16_t* tcand, const float* tchc, int R) {
     const int n = s.n, cl = s.cl;
@@ -642,7 +642,9 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
     // block of step k0 + l / G, slots 4(l % G) .. 4(l % G) + 3, and store
     // their logarithms at lnbuf[4l .. 4l + 3]; step k0 + j reads slot r at
     // lnbuf[4jG + r].
-    const int gsh = cl <= 4 ? 0 : cl <= 8 ? 1 : cl <= 16 ? 2 : cl <= 32 ? 3 : 4;
+    // (kG > 0: G fixed at compile time, with the draws pipelined below)
+    const int gsh = kG == 1 ? 0 : kG == 2 ? 1 : kG == 4 ? 2 : kG == 8 ? 3 : kG == 16 ? 4
+                  : cl <= 4 ? 0 : cl <= 8 ? 1 : cl <= 16 ? 2 : cl <= 32 ? 3 : 4;
     const int G = 1 << gsh;
     const int S = kWave >> gsh;
     const int lr = lane < cl ? lane : cl - 1;       // lanes past the list repeat the last entry
@@ -696,86 +698,158 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
         return next < (uint32_t)n ? next : 0u;
     };
 
-    // the whole tour; kCand: with a candidate list (the loop is instantiated
-    // once with it and once without, so the step has no test for it)
-    auto tour = [&](auto cand) {
-        constexpr bool kCand = decltype(cand)::value;
-        for (int k0 = 0; k0 < n; k0 += S) {
-            if constexpr (kCand) {
-                const Words4 b = draw_block(seed, it, (uint32_t)ant, (uint32_t)(k0 + (lane >> gsh)),
-                                            (uint32_t)(4 * (lane & (G - 1))));
-                float4 lv;
-                lv.x = log_u01(u01(b.w[0]));
-                lv.y = log_u01(u01(b.w[1]));
-                lv.z = log_u01(u01(b.w[2]));
-                lv.w = log_u01(u01(b.w[3]));
-                *reinterpret_cast<float4*>(lnbuf + 4 * lane) = lv;
+    // marks the chosen city, records it as step k and moves there
+    auto advance = [&](uint32_t next, int k) {
+        if constexpr (kTabu == MMAS_TABU_BITMASK) {
+            // every lane issues the OR, so that no exec mask is set up around
+            // it: lane 0 into the city's word, the others a 0 into their own
+            // word of the draw buffer (no change)
+            const uint32_t off = mark_base + mark_is0 * ((next >> 5) << 2);
+            atomicOr(reinterpret_cast<uint32_t*>(region + off), (1u << (next & 31u)) & mark_mask);
+        } else {
+            tabu.mark(next, lane);
+        }
+        if (lane == (k & 63)) tbuf = next;
+        cur = __builtin_amdgcn_readfirstlane((int)next);
+    };
+
+    // One candidate-phase step k reading its draws at lnbuf[4jG + r]; `mid`
+    // runs between the row loads and their first use (independent work that
+    // fills their latency).
+    auto cand_step = [&](int k, int j, auto&& mid) {
+        const int e = cur * cl + lr;
+        uint32_t node;
+        float w;
+        if (__builtin_expect(cur < R, 1)) {
+            node = lds_cand[e];
+            w = lds_chc[e];
+        } else {
+            node = glb_cand[e];
+            w = glb_chc[e];
+        }
+        mid();
+        const float lnu = lds_ln[4 * j * G + ln_lane];
+        const uint32_t live = tabu.live(node);
+        float key = lnu / w;
+        asm volatile("" : "+v"(key));
+        // ln(u) < 0 and w >= 0 give a key with the sign bit set (a negative
+        // number, -0 or -inf), whose order code is ~bits
+        const uint32_t code = ~__float_as_uint(key) & live & lane_ok;
+        const uint32_t best = wave_max_u32<kRows>(code);
+        uint32_t next = kNone;
+        if (best != 0u) {
+            const uint64_t tied = __ballot(code == best);
+            const int first = (int)__builtin_ctzll(tied);
+            next = (uint32_t)__builtin_amdgcn_readlane((int)node, first);
+            if (__builtin_expect(first != 63 - (int)__builtin_clzll(tied), 0))
+                next = wave_min_u32<kRows>(code == best ? node : kNone);
+        }
+        if (__builtin_expect(next == kNone, 0)) next = fallback(k);
+        advance(next, k);
+    };
+
+    // after the steps before ke: at the end of a 64-step chunk or of the
+    // tour, store the chunk's cities and add the lengths of the edges into them
+    auto flush = [&](int ke) {
+        if ((ke & 63) == 0 || ke == n) {
+            // steps c0 .. ke - 1; lane l holds step c0 + l
+            const int c0 = (ke - 1) & ~63;
+            const int last = ke - 1 - c0;
+            const uint32_t prev = __shfl_up(tbuf, 1);
+            if (lane <= last) {
+                tour_out[c0 + lane] = (uint16_t)tbuf;
+                // edge entering step c0 + l (none for step 0)
+                const uint32_t from = lane == 0 ? prev_last : prev;
+                if (c0 + lane > 0) len += dist[(size_t)from * n + tbuf];
             }
-            const int kb = k0 > 0 ? k0 : 1;
-            const int ke = k0 + S < n ? k0 + S : n;
-            for (int k = kb; k < ke; ++k) {
-                uint32_t next = kNone;
-                if constexpr (kCand) {
-                    const int e = cur * cl + lr;
-                    uint32_t node;
-                    float w;
-                    if (__builtin_expect(cur < R, 1)) {
-                        node = lds_cand[e];
-                        w = lds_chc[e];
-                    } else {
-                        node = glb_cand[e];
-                        w = glb_chc[e];
-                    }
-                    const float lnu = lds_ln[4 * (k - k0) * G + ln_lane];
-                    const uint32_t live = tabu.live(node);
-                    float key = lnu / w;
-                    asm volatile("" : "+v"(key));
-                    // ln(u) < 0 and w >= 0 give a key with the sign bit set
-                    // (a negative number, -0 or -inf), whose order code is ~bits
-                    const uint32_t code = ~__float_as_uint(key) & live & lane_ok;
-                    const uint32_t best = wave_max_u32<kRows>(code);
-                    if (best != 0u) {
-                        const uint64_t tied = __ballot(code == best);
-                        const int first = (int)__builtin_ctzll(tied);
-                        next = (uint32_t)__builtin_amdgcn_readlane((int)node, first);
-                        if (__builtin_expect(first != 63 - (int)__builtin_clzll(tied), 0))
-                            next = wave_min_u32<kRows>(code == best ? node : kNone);
-                    }
-                    if (__builtin_expect(next == kNone, 0)) next = fallback(k);
-                } else {
-                    next = fallback(k);
-                }
-                if constexpr (kTabu == MMAS_TABU_BITMASK) {
-                    // every lane issues the OR, so that no exec mask is set up
-                    // around it: lane 0 into the city's word, the others a 0
-                    // into their own word of the draw buffer (no change)
-                    const uint32_t off = mark_base + mark_is0 * ((next >> 5) << 2);
-                    atomicOr(reinterpret_cast<uint32_t*>(region + off), (1u << (next & 31u)) & mark_mask);
-                } else {
-                    tabu.mark(next, lane);
-                }
-                if (lane == (k & 63)) tbuf = next;
-                cur = __builtin_amdgcn_readfirstlane((int)next);
-            }
-            if ((ke & 63) == 0 || ke == n) {
-                // flush steps c0 .. ke - 1 of this chunk; lane l holds step c0 + l
-                const int c0 = (ke - 1) & ~63;
-                const int last = ke - 1 - c0;
-                const uint32_t prev = __shfl_up(tbuf, 1);
-                if (lane <= last) {
-                    tour_out[c0 + lane] = (uint16_t)tbuf;
-                    // edge entering step c0 + l (none for step 0)
-                    const uint32_t from = lane == 0 ? prev_last : prev;
-                    if (c0 + lane > 0) len += dist[(size_t)from * n + tbuf];
-                }
-                prev_last = (uint32_t)__builtin_amdgcn_readlane((int)tbuf, last);
-            }
+            prev_last = (uint32_t)__builtin_amdgcn_readlane((int)tbuf, last);
         }
     };
-    if (cl > 0)
-        tour(std::integral_constant<bool, true>{});
-    else
-        tour(std::integral_constant<bool, false>{});
+
+    // the draws of the group of steps k0 .. k0 + S - 1, all at once
+    auto draws_now = [&](int k0) {
+        const Words4 b = draw_block(seed, it, (uint32_t)ant, (uint32_t)(k0 + (lane >> gsh)),
+                                    (uint32_t)(4 * (lane & (G - 1))));
+        float4 lv;
+        lv.x = log_u01(u01(b.w[0]));
+        lv.y = log_u01(u01(b.w[1]));
+        lv.z = log_u01(u01(b.w[2]));
+        lv.w = log_u01(u01(b.w[3]));
+        *reinterpret_cast<float4*>(lnbuf + 4 * lane) = lv;
+    };
+
+    // steps kb .. ke - 1 of the group starting at k0 (draws in place)
+    auto steps_plain = [&](int k0, int kb, int ke) {
+        for (int k = kb; k < ke; ++k) cand_step(k, k - k0, [] {});
+    };
+
+    if (cl == 0) {
+        for (int k = 1; k < n; ++k) {
+            advance(fallback(k), k);
+            flush(k + 1);
+        }
+    } else if constexpr (kG > 0) {
+        // Draws computed one group ahead, spread over the steps of the group
+        // before in seven pieces (three of Philox rounds, the last round with
+        // the first logarithm, one logarithm each) that fill the latency of
+        // the steps' row loads, and stored after that group's last read.
+        constexpr int S = kWave / kG;
+        static_assert(S == 8 || S == 16, "pieces are laid out for 8 or 16 steps a group");
+        const uint32_t k0s = (uint32_t)seed, k1s = (uint32_t)(seed >> 32);
+        draws_now(0);
+        steps_plain(0, 1, S < n ? S : n);
+        flush(S < n ? S : n);
+        if (S < n) draws_now(S);
+        int k0 = S;
+        for (; k0 + S <= n; k0 += S) {
+            Words4 c;
+            float lv[4];
+            const int kn = k0 + S;  // the group whose draws are computed here
+#pragma unroll
+            for (int j = 0; j < S; ++j) {
+                // piece q of the next group's draws runs at step j = q * S / 8
+                auto piece = [&] {
+                    if (j * 8 % S != 0) return;
+                    const int q = j * 8 / S;
+                    // (each piece's results pass through an empty asm in this
+                    // step, which keeps the compiler from sinking the piece to
+                    // the end of the group, where its results are stored)
+                    if (q == 0) {
+                        c = Words4{{(uint32_t)(lane & (kG - 1)) | ((uint32_t)(kn + (lane >> gsh)) << 16),
+                                    (uint32_t)ant, it, 0u}};
+                        philox_rounds<0, 3>(c, k0s, k1s);
+                    } else if (q == 1) {
+                        philox_rounds<3, 6>(c, k0s, k1s);
+                    } else if (q == 2) {
+                        philox_rounds<6, 9>(c, k0s, k1s);
+                    } else if (q == 3) {
+                        philox_rounds<9, 10>(c, k0s, k1s);
+                        lv[0] = log_u01(u01(c.w[0]));
+                        asm volatile("" : "+v"(lv[0]));
+                    } else if (q < 7) {
+                        lv[q - 3] = log_u01(u01(c.w[q - 3]));
+                        asm volatile("" : "+v"(lv[q - 3]));
+                    }
+                    if (q < 4) asm volatile("" : "+v"(c.w[0]), "+v"(c.w[1]), "+v"(c.w[2]), "+v"(c.w[3]));
+                };
+                cand_step(k0 + j, j, piece);
+            }
+            // after the group's last read of the buffer
+            *reinterpret_cast<float4*>(lnbuf + 4 * lane) = make_float4(lv[0], lv[1], lv[2], lv[3]);
+            flush(k0 + S);
+        }
+        if (k0 < n) {
+            steps_plain(k0, k0, n);
+            flush(n);
+        }
+    } else {
+        for (int k0 = 0; k0 < n; k0 += S) {
+            draws_now(k0);
+            const int ke = k0 + S < n ? k0 + S : n;
+            steps_plain(k0, k0 > 0 ? k0 : 1, ke);
+            flush(ke);
+        }
+    }
     if (bad && lane == 0) atomicOr(&vw.state->flags, 8u);
     if (lane == 0) len += dist[(size_t)cur * n + start];  // closing edge
     len = wave_sum_i64(len);
@@ -974,8 +1048,10 @@ __device__ void construct_pair(const Views& vw, const Shape& s, uint32_t it, int
 }
 
 // kRows: 16-lane rows the argmax of a one-ant-per-wave step reduces (2 for
-// cl <= 32, else 4); unused with two ants per wave.
-template <int kTabu, int kPher, bool kPair, int kRows = 4>
+// cl <= 32, else 4); kG: 4-slot draw groups per step when fixed (4 for
+// 9 <= cl <= 16, 8 for 17 <= cl <= 32: the draws are then pipelined), else 0.
+// Both unused with two ants per wave.
+template <int kTabu, int kPher, bool kPair, int kRows = 4, int kG = 0>
 __global__ __launch_bounds__(1024) void k_construct(Views vw, Shape s, uint32_t it, int ants_per_block, Lds lds) {
     extern __shared__ __align__(16) uint8_t smem[];
     const int lane = threadIdx.x & 63;
@@ -994,8 +1070,8 @@ __global__ __launch_bounds__(1024) void k_construct(Views vw, Shape s, uint32_t 
         construct_pair<kTabu, kPher>(vw, s, it, ant, ant + 1 < s.ants, lane, regions + (size_t)(2 * wave) * lds.per_ant,
                                      regions + (size_t)(2 * wave + 1) * lds.per_ant, tcand, tchc, R);
     else
-        construct_lone<kTabu, kPher, kRows>(vw, s, it, ant, lane, regions + (size_t)wave * lds.per_ant, tcand, tchc,
-                                            R);
+        construct_lone<kTabu, kPher, kRows, kG>(vw, s, it, ant, lane, regions + (size_t)wave * lds.per_ant, tcand,
+                                                tchc, R);
 }
 
 // One ant per workgroup of several waves (construct_ant with kWide): the
@@ -1091,7 +1167,7 @@ namespace {
 // in a half wave).
 bool pair_ok(const Shape& s) { return s.lanes_per_ant == 32 && s.cl >= 1 && s.cl <= 32; }
 
-template <int kTabu, int kPher, bool kPair, int kRows = 4>
+template <int kTabu, int kPher, bool kPair, int kRows = 4, int kG = 0>
 hipError_t launch_t(const Views& v, const Shape& s0, uint32_t it, hipStream_t st) {
     // one colony: a workgroup per four ants rarely shares a CU, so the fallback
     // lists every unvisited city in one pass
@@ -1132,7 +1208,7 @@ hipError_t launch_t(const Views& v, const Shape& s0, uint32_t it, hipStream_t st
     lds.rows = rows;
     lds.table_bytes = align16(rows * s.cl * 2) + align16(rows * s.cl * 4);
     const size_t bytes = (size_t)lds.table_bytes + (size_t)apb * per_ant;
-    auto kern = k_construct<kTabu, kPher, kPair, kRows>;
+    auto kern = k_construct<kTabu, kPher, kPair, kRows, kG>;
     if (bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
@@ -1194,6 +1270,8 @@ hipError_t launch_tp(const Views& v, const Shape& s, uint32_t it, hipStream_t st
     if (pair_ok(s)) return launch_t<kTabu, kPher, true>(v, s, it, st);
     const int waves = construct_waves(s);
     if (waves > 1) return launch_wide<kTabu, kPher>(v, s, it, waves, st);
+    if (s.cl > 16 && s.cl <= 32) return launch_t<kTabu, kPher, false, 2, 8>(v, s, it, st);
+    if (s.cl > 8 && s.cl <= 16) return launch_t<kTabu, kPher, false, 2, 4>(v, s, it, st);
     if (s.cl <= 32) return launch_t<kTabu, kPher, false, 2>(v, s, it, st);
     return launch_t<kTabu, kPher, false, 4>(v, s, it, st);
 }

@@ -20,23 +20,32 @@ struct Words4 {
     uint32_t w[4];
 };
 
+// Rounds r0 .. r1 - 1 of Philox4x32-10 on the counter c with the key
+// (k0, k1) of round 0 (round r uses k + r times the Weyl constants), so that
+// the ten rounds can be spread over several calls.
+template <int r0, int r1>
+__device__ __forceinline__ void philox_rounds(Words4& c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = r0; round < r1; ++round) {
+        const uint32_t rk0 = k0 + (uint32_t)round * 0x9E3779B9u;
+        const uint32_t rk1 = k1 + (uint32_t)round * 0xBB67AE85u;
+        // one 32x32 -> 64-bit multiply each (v_mad_u64_u32) gives hi and lo
+        const uint64_t p0 = (uint64_t)c.w[0] * 0xD2511F53u;
+        const uint64_t p1 = (uint64_t)c.w[2] * 0xCD9E8D57u;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c.w[1] ^ rk0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c.w[3] ^ rk1;
+        c.w[0] = n0;
+        c.w[1] = (uint32_t)p1;
+        c.w[2] = n2;
+        c.w[3] = (uint32_t)p0;
+    }
+}
+
 __device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                 uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int round = 0; round < 10; ++round) {
-        // one 32x32 -> 64-bit multiply each (v_mad_u64_u32) gives hi and lo
-        const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
-        const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
-        c0 = n0;
-        c1 = (uint32_t)p1;
-        c2 = n2;
-        c3 = (uint32_t)p0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return Words4{{c0, c1, c2, c3}};
+    Words4 c{{c0, c1, c2, c3}};
+    philox_rounds<0, 10>(c, k0, k1);
+    return c;
 }
 
 // The Philox block that holds draw `slot` of (iteration, ant, step): counter

@@ -117,6 +117,17 @@ CASES = [
     ("cand_mode_cl1", "clustered", 150, 10, dict(ants=20, cand_len=1, pher="candidates", rho=0.5)),
     ("one_ant", "uniform", 500, 11, dict(ants=1, cand_len=16)),
     ("ants_not_mult4", "uniform", 199, 12, dict(ants=1003 % 64 + 3, cand_len=32)),
+    # group boundaries of the draws computed one group ahead (8 steps a group
+    # for 17 <= cl <= 32, 16 for 9 <= cl <= 16): a tour of exactly two groups,
+    # one step more, a whole number of groups, and one step past a 64-step
+    # chunk of the tour
+    ("groups_n24_cl20", "uniform", 24, 13, dict(ants=24, cand_len=20)),
+    ("groups_n25_cl20", "clustered", 25, 14, dict(ants=24, cand_len=20)),
+    ("groups_n21_cl20", "uniform", 21, 19, dict(ants=24, cand_len=20)),
+    ("groups_n32_cl12", "uniform", 32, 15, dict(ants=24, cand_len=12)),
+    ("groups_n33_cl12", "clustered", 33, 16, dict(ants=24, cand_len=12)),
+    ("groups_n65_cl24", "uniform", 65, 17, dict(ants=40, cand_len=24)),
+    ("groups_n129_cl16", "clustered", 129, 18, dict(ants=40, cand_len=16)),
 ]
 
 
