@@ -14,15 +14,17 @@
  *  - Device memory: the caller owns one device buffer (the workspace, at
  *    least mmas_workspace_bytes() bytes, 256-byte aligned) and lends it to the
  *    context from mmas_create until mmas_destroy. The library allocates no
- *    device memory of its own.
+ *    device memory of its own (its one static device array serves
+ *    mmas_mlp_features_noalloc).
  *  - Streams: every call enqueues on the hipStream_t given to mmas_create and
  *    returns without waiting, except where a call says it synchronises.
  *  - Errors: every call returns a status and never aborts. Kernel faults show
  *    up as MMAS_EHIP at the next synchronising call.
  *  - Determinism: one (distance matrix, parameters, seed, iteration) has
  *    exactly one result. Every random number is drawn from Philox4x32-10
- *    keyed on (seed, iteration, ant, step, slot); keys are ln(u)/w in FP32
- *    with IEEE division; equal keys go to the lowest node index. The tabu
+ *    keyed on (seed, iteration, ant, step, slot); keys are ln(u) * (1/w) in
+ *    FP32 (the reciprocal by IEEE division, computed ahead as Sec. 4.2.2
+ *    suggests, then one product); equal keys go to the lowest node index. The tabu
  *    variant and the launch shape never change a result.
  *  - Threading: a context is not thread-safe; separate contexts are
  *    independent.

@@ -513,10 +513,12 @@ static int select_prwm(const orc_colony* c, int cur, const uint8_t* visited, uin
 }
 
 /* Node selection by weighted reservoir sampling (Alg. 4, Sec. 4.2.2): every
- * eligible node v draws u and gets the key ln(u)/w_v; the largest key wins
- * (a reservoir of size one); equal keys go to the lowest node index. The
- * eligible set is the unvisited part of the candidate list of `cur`
- * (Sec. 4.3); when it is empty, every unvisited node. */
+ * eligible node v draws u and gets the key ln(u) * (1/w_v), the logarithm of
+ * Sec. 4.2.2 times the weight's reciprocal, which that section suggests
+ * computing in advance (here: one IEEE division, then one product); the
+ * largest key wins (a reservoir of size one); equal keys go to the lowest
+ * node index. The eligible set is the unvisited part of the candidate list
+ * of `cur` (Sec. 4.3); when it is empty, every unvisited node. */
 int orc_select_next(const orc_colony* c, int cur, const uint8_t* visited, uint32_t it, uint32_t ant,
                     uint32_t step, int* fallback) {
     if (c->select == ORC_SELECT_PRWM) return select_prwm(c, cur, visited, it, ant, step, fallback);
@@ -527,7 +529,8 @@ int orc_select_next(const orc_colony* c, int cur, const uint8_t* visited, uint32
         int v = c->cand[(size_t)cur * cl + r];
         if (visited[v]) continue;
         float u = orc_u01(orc_draw_word(c->seed, it, ant, step, (uint32_t)r));
-        float key = orc_logf(u) / c->chc[(size_t)cur * cl + r];
+        float recip = 1.0f / c->chc[(size_t)cur * cl + r];
+        float key = orc_logf(u) * recip;
         if (best < 0 || key > best_key || (key == best_key && v < best)) {
             best = v;
             best_key = key;
@@ -539,7 +542,8 @@ int orc_select_next(const orc_colony* c, int cur, const uint8_t* visited, uint32
     for (int v = 0; v < c->n; ++v) {
         if (visited[v]) continue;
         float u = orc_u01(orc_draw_word(c->seed, it, ant, step, (uint32_t)(cl + v)));
-        float key = orc_logf(u) / fallback_weight(c, cur, v);
+        float recip = 1.0f / fallback_weight(c, cur, v);
+        float key = orc_logf(u) * recip;
         if (best < 0 || key > best_key || (key == best_key && v < best)) {
             best = v;
             best_key = key;

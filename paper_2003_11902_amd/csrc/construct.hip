@@ -1,7 +1,8 @@
 // Tour construction (the inner loops of Alg. 1): one ant per wave64.
 //
 // Each step selects the next city by weighted reservoir sampling (Alg. 4):
-// every eligible city v draws u and gets the key ln(u) / w(cur, v); the wave
+// every eligible city v draws u and gets the key ln(u) * (1 / w(cur, v)), the
+// reciprocal of the weight computed ahead as Sec. 4.2.2 suggests; the wave
 // keeps the largest key, the lowest city among equal keys. Eligible are the
 // unvisited cities of the current city's candidate list (Sec. 4.3), one per
 // lane, with w = choice_info along the list; when all are visited, every
@@ -191,7 +192,7 @@ __device__ __forceinline__ void fallback_keys(const uint16_t* list, int L, const
             if (v[u] == kNone) continue;
             const uint32_t slot = (uint32_t)cl + v[u];
             const Words4 blk = draw_block(seed, it, ant, step, slot);
-            const float key = log_u01(u01(pick_word(blk, slot & 3u))) / w[u];
+            const float key = log_u01(u01(pick_word(blk, slot & 3u))) * (1.0f / w[u]);
             keep_best(ord_key(key), v[u], bcode, bnode);
         }
     }
@@ -339,7 +340,7 @@ __device__ __forceinline__ unsigned long long fallback_share(const uint16_t* lis
             if (v[u] == kNone) continue;
             const uint32_t slot = (uint32_t)cl + v[u];
             const Words4 blk = draw_block(seed, it, ant, step, slot);
-            const float key = log_u01(u01(pick_word(blk, slot & 3u))) / w[u];
+            const float key = log_u01(u01(pick_word(blk, slot & 3u))) * (1.0f / w[u]);
             keep_best(ord_key(key), v[u], bcode, bnode);
         }
     }
@@ -366,7 +367,7 @@ __device__ __forceinline__ unsigned long long fallback_share_blocks(const T& tab
             for (int j = 0; j < 4; ++j) {
                 const int v = 4 * b + j - cl;
                 if (v < 0 || v >= n || tabu.visited((uint32_t)v)) continue;
-                const float key = log_u01(u01(blk.w[j])) / weight((uint32_t)v);
+                const float key = log_u01(u01(blk.w[j])) * (1.0f / weight((uint32_t)v));
                 keep_best(ord_key(key), (uint32_t)v, bcode, bnode);
             }
         }
@@ -386,12 +387,12 @@ struct Lds {
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 
 // The whole workgroup copies the first R rows of the candidate table (ids,
-// then choice_info) into LDS; the caller synchronises.
+// then the reciprocals of choice_info) into LDS; the caller synchronises.
 __device__ void stage_table(const Views& vw, int cl, int R, uint16_t* tcand, float* tchc) {
     const int ne = R * cl;
     for (int e = threadIdx.x; e < ne; e += blockDim.x) {
         tcand[e] = vw.cand[e];
-        tchc[e] = vw.chc[e];
+        tchc[e] = vw.chc_inv[e];
     }
 }
 
@@ -424,7 +425,7 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
     const LdsPtr<const uint16_t> lds_cand = (LdsPtr<const uint16_t>)tcand;
     const LdsPtr<const float> lds_chc = (LdsPtr<const float>)tchc;
     const GlbPtr<const uint16_t> glb_cand = (GlbPtr<const uint16_t>)vw.cand;
-    const GlbPtr<const float> glb_chc = (GlbPtr<const float>)vw.chc;
+    const GlbPtr<const float> glb_chc = (GlbPtr<const float>)vw.chc_inv;  // reciprocals
 
     // start city: floor(x * n / 2^32) of draw (step 0, slot 0)
     const uint32_t x0 = draw_block(seed, it, (uint32_t)ant, 0u, 0u).w[0];
@@ -483,7 +484,7 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
             // the visited-bit load is issued first, then every lane divides (no
             // exec mask), so that the division overlaps the load
             const bool seen = tabu.visited(node);
-            float key = lnu / w;
+            float key = lnu * w;  // (w holds 1 / choice_info)
             asm volatile("" : "+v"(key));
             const bool live = (lane < cl) & !seen;  // no short circuit: no exec mask
             const uint32_t code = live ? ord_key(key) : 0u;
@@ -629,7 +630,7 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
     const LdsPtr<const uint16_t> lds_cand = (LdsPtr<const uint16_t>)tcand;
     const LdsPtr<const float> lds_chc = (LdsPtr<const float>)tchc;
     const GlbPtr<const uint16_t> glb_cand = (GlbPtr<const uint16_t>)vw.cand;
-    const GlbPtr<const float> glb_chc = (GlbPtr<const float>)vw.chc;
+    const GlbPtr<const float> glb_chc = (GlbPtr<const float>)vw.chc_inv;  // reciprocals
     const LdsPtr<const float> lds_ln = (LdsPtr<const float>)lnbuf;
 
     const uint32_t x0 = draw_block(seed, it, (uint32_t)ant, 0u, 0u).w[0];
@@ -730,7 +731,7 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
         mid();
         const float lnu = lds_ln[4 * j * G + ln_lane];
         const uint32_t live = tabu.live(node);
-        float key = lnu / w;
+        float key = lnu * w;  // (w holds 1 / choice_info)
         asm volatile("" : "+v"(key));
         // ln(u) < 0 and w >= 0 give a key with the sign bit set (a negative
         // number, -0 or -inf), whose order code is ~bits
@@ -929,7 +930,7 @@ __device__ void construct_pair(const Views& vw, const Shape& s, uint32_t it, int
     const LdsPtr<const uint16_t> lds_cand = (LdsPtr<const uint16_t>)tcand;
     const LdsPtr<const float> lds_chc = (LdsPtr<const float>)tchc;
     const GlbPtr<const uint16_t> glb_cand = (GlbPtr<const uint16_t>)vw.cand;
-    const GlbPtr<const float> glb_chc = (GlbPtr<const float>)vw.chc;
+    const GlbPtr<const float> glb_chc = (GlbPtr<const float>)vw.chc_inv;  // reciprocals
 
     // start cities: floor(x * n / 2^32) of draw (step 0, slot 0) of each ant
     const uint32_t x0 = draw_block(seed, it, my_ant, 0u, 0u).w[0];
@@ -977,7 +978,7 @@ __device__ void construct_pair(const Views& vw, const Shape& s, uint32_t it, int
             *reinterpret_cast<float4*>(lnbuf + 4 * hl) = lv;
         }
         const float lnu = lnbuf[4 * j * G + (hl & (4 * G - 1))];
-        float key = lnu / w;
+        float key = lnu * w;  // (w holds 1 / choice_info)
         asm volatile("" : "+v"(key));  // every lane divides, overlapping the visited-bit load
         const Tabu mine = h ? tabB : tabA;  // this half's tabu
         const bool live = (hl < cl) & !mine.visited(node) & writer;

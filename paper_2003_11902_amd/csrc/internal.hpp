@@ -17,6 +17,7 @@ struct Views {
     float* tau;         // n*n (dense) or n*cl (candidates)
     float* choice;      // n*n (dense) or nullptr
     float* chc;         // n*cl
+    float* chc_inv;     // n*cl: 1 / chc (IEEE division), the key's factor
     uint16_t* cand;     // n*cl
     uint16_t* lsnn;     // n*ls_nn or nullptr
     uint16_t* tours;    // ants*n

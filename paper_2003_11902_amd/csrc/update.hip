@@ -1,5 +1,7 @@
 // Per-iteration kernels around construction (Alg. 1, Sec. 2.1):
-//  - choice_info = tau^alpha * eta^beta, dense and along the candidate lists;
+//  - choice_info = tau^alpha * eta^beta, dense and along the candidate lists,
+//    and along the lists also its reciprocal (Sec. 4.2.2: the reciprocal of
+//    every weight computed once per iteration, so that a key is a product);
 //  - the iteration best, the global best and the trail limits (one workgroup);
 //  - evaporation, deposit on both directions of the iteration best's edges (on
 //    (i, succ(i)) alone for the asymmetric TSP) and the [tau_min, tau_max] clamp, fused with the refresh of choice_info (the
@@ -14,7 +16,8 @@ namespace {
 // dense: one workgroup per row
 __global__ __launch_bounds__(256) void k_choice_dense(const float* __restrict__ tau, const float* __restrict__ heur,
                                                       const uint16_t* __restrict__ cand, int n, int cl, int alpha,
-                                                      float* __restrict__ choice, float* __restrict__ chc) {
+                                                      float* __restrict__ choice, float* __restrict__ chc,
+                                                      float* __restrict__ chc_inv) {
     const size_t i = blockIdx.x;
     const float* trow = tau + i * n;
     const float* hrow = heur + i * n;
@@ -22,15 +25,21 @@ __global__ __launch_bounds__(256) void k_choice_dense(const float* __restrict__ 
     for (int j = threadIdx.x; j < n; j += blockDim.x) crow[j] = powi(trow[j], alpha) * hrow[j];
     for (int r = threadIdx.x; r < cl; r += blockDim.x) {
         const int j = cand[i * cl + r];
-        chc[i * cl + r] = powi(trow[j], alpha) * hrow[j];
+        const float c = powi(trow[j], alpha) * hrow[j];
+        chc[i * cl + r] = c;
+        chc_inv[i * cl + r] = 1.0f / c;
     }
 }
 
 // candidate-only trails: heur is n*cl along the lists
 __global__ __launch_bounds__(256) void k_choice_cand(const float* __restrict__ tau, const float* __restrict__ heur,
-                                                     size_t count, int alpha, float* __restrict__ chc) {
-    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x)
-        chc[e] = powi(tau[e], alpha) * heur[e];
+                                                     size_t count, int alpha, float* __restrict__ chc,
+                                                     float* __restrict__ chc_inv) {
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x) {
+        const float c = powi(tau[e], alpha) * heur[e];
+        chc[e] = c;
+        chc_inv[e] = 1.0f / c;
+    }
 }
 
 // Iteration best = shortest tour, lowest ant on ties. If it beats the global
@@ -137,7 +146,9 @@ __device__ void update_dense_row(const Views& vw, const Shape& s, size_t i) {
     for (int r = threadIdx.x; r < cl; r += blockDim.x) {
         const int j = vw.cand[i * cl + r];
         const float t = evaporate_deposit(trow[j], j == si || j == pi, keep, tmin, tmax, delta);
-        vw.chc[i * cl + r] = powi(t, s.alpha) * hrow[j];
+        const float c = powi(t, s.alpha) * hrow[j];
+        vw.chc[i * cl + r] = c;
+        vw.chc_inv[i * cl + r] = 1.0f / c;
     }
     __syncthreads();
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
@@ -158,7 +169,9 @@ __device__ void update_cand_row(const Views& vw, const Shape& s, size_t i) {
         const int j = vw.cand[e];
         const float t = evaporate_deposit(vw.tau[e], j == si || j == pi, keep, tmin, tmax, delta);
         vw.tau[e] = t;
-        vw.chc[e] = powi(t, s.alpha) * vw.heur[e];
+        const float c = powi(t, s.alpha) * vw.heur[e];
+        vw.chc[e] = c;
+        vw.chc_inv[e] = 1.0f / c;
     }
 }
 
@@ -203,7 +216,9 @@ __global__ __launch_bounds__(256) void k_update_cand(Views vw, Shape s) {
         const bool dep = j == vw.succ[i] || (!s.directed && j == vw.pred[i]);
         const float t = evaporate_deposit(vw.tau[e], dep, keep, tmin, tmax, delta);
         vw.tau[e] = t;
-        vw.chc[e] = powi(t, s.alpha) * vw.heur[e];
+        const float c = powi(t, s.alpha) * vw.heur[e];
+        vw.chc[e] = c;
+        vw.chc_inv[e] = 1.0f / c;
     }
 }
 
@@ -218,10 +233,10 @@ int grid_for(size_t total, int block) {
 
 hipError_t launch_choice(const Views& v, const Shape& s, hipStream_t st) {
     if (s.pher == MMAS_PHER_DENSE) {
-        k_choice_dense<<<s.n, 256, 0, st>>>(v.tau, v.heur, v.cand, s.n, s.cl, s.alpha, v.choice, v.chc);
+        k_choice_dense<<<s.n, 256, 0, st>>>(v.tau, v.heur, v.cand, s.n, s.cl, s.alpha, v.choice, v.chc, v.chc_inv);
     } else {
         const size_t count = (size_t)s.n * s.cl;
-        k_choice_cand<<<grid_for(count, 256), 256, 0, st>>>(v.tau, v.heur, count, s.alpha, v.chc);
+        k_choice_cand<<<grid_for(count, 256), 256, 0, st>>>(v.tau, v.heur, count, s.alpha, v.chc, v.chc_inv);
     }
     return hipGetLastError();
 }
