@@ -255,20 +255,71 @@ __device__ __forceinline__ uint32_t fallback_bitmask(const BitmaskTabu& tabu, in
     return wave_select<4>(bcode, bnode);
 }
 
-// The same as calls (not inlined): the single-colony kernel, whose one wave
-// per SIMD is bound by its per-step chain, keeps its step loop small this way.
-template <class W>
-__device__ __attribute__((noinline)) uint32_t fallback_list_call(const uint16_t* list, int L, const W& weight, int cl,
-                                                                 uint64_t seed, uint32_t it, uint32_t ant,
-                                                                 uint32_t step, int lane) {
-    return fallback_list(list, L, weight, cl, seed, it, ant, step, lane);
-}
-template <class W>
-__device__ __attribute__((noinline)) uint32_t fallback_bitmask_call(const BitmaskTabu& tabu, int n, uint16_t* list,
-                                                                    int cap, const W& weight, int cl, uint64_t seed,
-                                                                    uint32_t it, uint32_t ant, uint32_t step,
-                                                                    int lane) {
-    return fallback_bitmask(tabu, n, list, cap, weight, cl, seed, it, ant, step, lane);
+// The all-node fallback of the single-colony kernel, outlined (it is rare
+// with a list, and one copy serves every step of the unrolled step loop):
+// the same keys and winner as fallback_bitmask / fallback_list, but with the
+// LDS list and the global weight row passed with their address spaces (an
+// outlined function would otherwise reach both through flat accesses) and a
+// lane's four list entries keyed without branches. kList: the tabu lists the
+// unvisited cities itself (`list`, L entries); otherwise the bitmask `bits`
+// (n cities) is listed into `list` first. Weights: wrow[v] (dense trails) or
+// tmin_a * eta(drow[v])^beta (candidate-only trails).
+template <bool kList, int kPher>
+__device__ __attribute__((noinline)) uint32_t fallback_lone(LdsPtr<const uint32_t> bits, LdsPtr<uint16_t> list, int L,
+                                                            int n, GlbPtr<const float> wrow,
+                                                            GlbPtr<const int32_t> drow, float tmin_a, int beta,
+                                                            int cl, uint64_t seed, uint32_t it, uint32_t ant,
+                                                            uint32_t step, int lane) {
+    if constexpr (!kList) {
+        // every unvisited city in ascending order (one pass: room for n)
+        const int words = (n + 31) >> 5;
+        L = 0;
+        for (int w0 = 0; w0 < words; w0 += kWave) {
+            const int wi = w0 + lane;
+            uint32_t fr = 0u;
+            if (wi < words) {
+                fr = ~bits[wi];
+                if (wi == words - 1 && (n & 31)) fr &= (1u << (n & 31)) - 1u;
+            }
+            const int cnt = __popc(fr);
+            const int incl = wave_incl_scan(cnt, lane);
+            int p = L + incl - cnt;
+            while (fr) {
+                const int b = __ffs(fr) - 1;
+                fr &= fr - 1u;
+                list[p++] = (uint16_t)(wi * 32 + b);
+            }
+            L += __builtin_amdgcn_readlane(incl, 63);
+        }
+    }
+    uint32_t bcode = 0u, bnode = kNone;
+    for (int base = 0; base < L; base += 4 * kWave) {
+        uint32_t v[4];
+        float w[4];
+        bool ok[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + u * kWave + lane;
+            ok[u] = i < L;
+            v[u] = list[ok[u] ? i : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if constexpr (kPher == MMAS_PHER_DENSE)
+                w[u] = wrow[v[u]];
+            else
+                w[u] = tmin_a * heur_from_dist(drow[v[u]], beta);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t slot = (uint32_t)cl + v[u];
+            const Words4 blk = draw_block(seed, it, ant, step, slot);
+            const float key = log_u01(u01(pick_word(blk, slot & 3u))) * (1.0f / w[u]);
+            const uint32_t code = ok[u] ? ord_key(key) : 0u;
+            keep_best(code, v[u], bcode, bnode);
+        }
+    }
+    return wave_select<4>(bcode, bnode);
 }
 
 // ---- several waves per ant: the fallback shared by the workgroup ----------
@@ -401,7 +452,7 @@ __device__ void stage_table(const Views& vw, int cl, int R, uint16_t* tcand, flo
 // candidate table are in LDS at tcand / tchc.
 // With kWide the whole workgroup serves one ant: wave 0 takes the steps and
 // the other waves join it for every fallback (wl: the workgroup's WideLds).
-template <int kTabu, int kPher, bool kWide = false, bool kOutline = false>
+template <int kTabu, int kPher, bool kWide = false>
 __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int ant, int lane, uint8_t* region,
                               const uint16_t* tcand, const float* tchc, int R, WideLds* wl = nullptr) {
     const int n = s.n, cl = s.cl;
@@ -558,19 +609,15 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
             if constexpr (kPher == MMAS_PHER_DENSE) {
                 const DenseWeight wt{vw.choice + (size_t)cur * n};
                 if constexpr (kTabu == MMAS_TABU_BITMASK)
-                    next = kOutline ? fallback_bitmask_call(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane)
-                                    : fallback_bitmask(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+                    next = fallback_bitmask(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
                 else
-                    next = kOutline ? fallback_list_call(tabu.list(), tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane)
-                                    : fallback_list(tabu.list(), tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+                    next = fallback_list(tabu.list(), tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
             } else {
                 const CandWeight wt{dist + (size_t)cur * n, tmin_a, s.beta};
                 if constexpr (kTabu == MMAS_TABU_BITMASK)
-                    next = kOutline ? fallback_bitmask_call(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane)
-                                    : fallback_bitmask(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+                    next = fallback_bitmask(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
                 else
-                    next = kOutline ? fallback_list_call(tabu.list(), tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane)
-                                    : fallback_list(tabu.list(), tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+                    next = fallback_list(tabu.list(), tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
             }
         }
         if (next >= (uint32_t)n) {
@@ -676,21 +723,18 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
         asm volatile("" : "+s"(kk));
         fb_steps += 1;
         fb_nodes += n - kk;
-        const int cap = list_cap(s);
+        // (C-style casts: the only casts that change the address space)
+        const GlbPtr<const float> wrow =
+            kPher == MMAS_PHER_DENSE ? (GlbPtr<const float>)(vw.choice + (size_t)cur * n) : nullptr;
+        const GlbPtr<const int32_t> drow =
+            kPher == MMAS_PHER_DENSE ? nullptr : (GlbPtr<const int32_t>)(dist + (size_t)cur * n);
         uint32_t pick;
-        if constexpr (kPher == MMAS_PHER_DENSE) {
-            const DenseWeight wt{vw.choice + (size_t)cur * n};
-            if constexpr (kTabu == MMAS_TABU_BITMASK)
-                pick = fallback_bitmask_call(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
-            else
-                pick = fallback_list_call(tabu.list(), tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
-        } else {
-            const CandWeight wt{dist + (size_t)cur * n, tmin_a, s.beta};
-            if constexpr (kTabu == MMAS_TABU_BITMASK)
-                pick = fallback_bitmask_call(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
-            else
-                pick = fallback_list_call(tabu.list(), tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
-        }
+        if constexpr (kTabu == MMAS_TABU_BITMASK)
+            pick = fallback_lone<false, kPher>((LdsPtr<const uint32_t>)tabu.bits, (LdsPtr<uint16_t>)ulist, 0, n, wrow,
+                                               drow, tmin_a, s.beta, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+        else
+            pick = fallback_lone<true, kPher>(nullptr, (LdsPtr<uint16_t>)tabu.list(), tabu.L, n, wrow, drow, tmin_a,
+                                              s.beta, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
         const uint32_t next = (uint32_t)__builtin_amdgcn_readfirstlane((int)pick);
         // no city is unreachable with a validated instance; were it not,
         // report it after the tour and go on with city 0 (the tour is void)

@@ -32,8 +32,9 @@ __device__ __forceinline__ void philox_rounds(Words4& c, uint32_t k0, uint32_t k
         // one 32x32 -> 64-bit multiply each (v_mad_u64_u32) gives hi and lo
         const uint64_t p0 = (uint64_t)c.w[0] * 0xD2511F53u;
         const uint64_t p1 = (uint64_t)c.w[2] * 0xCD9E8D57u;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c.w[1] ^ rk0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c.w[3] ^ rk1;
+        // three-input XORs in one instruction each (truth table 0x96)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c.w[1], rk0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c.w[3], rk1, 0x96);
         c.w[0] = n0;
         c.w[1] = (uint32_t)p1;
         c.w[2] = n2;
