@@ -271,15 +271,18 @@ __device__ __attribute__((noinline)) uint32_t fallback_lone(LdsPtr<const uint32_
                                                             int cl, uint64_t seed, uint32_t it, uint32_t ant,
                                                             uint32_t step, int lane) {
     if constexpr (!kList) {
-        // every unvisited city in ascending order (one pass: room for n)
-        const int words = (n + 31) >> 5;
+        // every unvisited city in ascending order (one pass: room for n),
+        // lane l taking 16-bit halves l, l + 64, ... of the bitmask, so that
+        // a lane writes at most 16 entries
+        const LdsPtr<const uint16_t> halves = (LdsPtr<const uint16_t>)bits;
+        const int nh = (n + 15) >> 4;
         L = 0;
-        for (int w0 = 0; w0 < words; w0 += kWave) {
-            const int wi = w0 + lane;
+        for (int h0 = 0; h0 < nh; h0 += kWave) {
+            const int hi = h0 + lane;
             uint32_t fr = 0u;
-            if (wi < words) {
-                fr = ~bits[wi];
-                if (wi == words - 1 && (n & 31)) fr &= (1u << (n & 31)) - 1u;
+            if (hi < nh) {
+                fr = ~(uint32_t)halves[hi] & 0xFFFFu;
+                if (hi == nh - 1 && (n & 15)) fr &= (1u << (n & 15)) - 1u;
             }
             const int cnt = __popc(fr);
             const int incl = wave_incl_scan(cnt, lane);
@@ -287,7 +290,7 @@ __device__ __attribute__((noinline)) uint32_t fallback_lone(LdsPtr<const uint32_
             while (fr) {
                 const int b = __ffs(fr) - 1;
                 fr &= fr - 1u;
-                list[p++] = (uint16_t)(wi * 32 + b);
+                list[p++] = (uint16_t)(hi * 16 + b);
             }
             L += __builtin_amdgcn_readlane(incl, 63);
         }
@@ -303,6 +306,7 @@ __device__ __attribute__((noinline)) uint32_t fallback_lone(LdsPtr<const uint32_
             ok[u] = i < L;
             v[u] = list[ok[u] ? i : 0];
         }
+        // the weight loads go out before the draws and their logarithms
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if constexpr (kPher == MMAS_PHER_DENSE)
