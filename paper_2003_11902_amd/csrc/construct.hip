@@ -952,12 +952,30 @@ __device__ uint32_t fallback_step(const Views& vw, const Shape& s, uint32_t it, 
     }
 }
 
+// The visited test of a lane's candidate in a wave serving two ants: lane
+// half h reads the tabu of its own ant (~0 if unvisited, else 0).
+__device__ __forceinline__ uint32_t live_pair(const BitmaskTabu& a, const BitmaskTabu& b, int h, uint32_t v) {
+    const uint32_t* bits = h ? b.bits : a.bits;
+    return __builtin_amdgcn_ubfe(bits[v >> 5], v, 1u) - 1u;
+}
+__device__ __forceinline__ uint32_t live_pair(const CompactTabu& a, const CompactTabu& b, int h, uint32_t v) {
+    const uint16_t* e = h ? b.entries : a.entries;
+    return e[v] > v ? 0u : ~0u;
+}
+__device__ __forceinline__ uint32_t live_pair(const ListTabu& a, const ListTabu& b, int h, uint32_t v) {
+    const uint16_t* idx = h ? b.idx : a.idx;
+    const int L = h ? b.L : a.L;
+    return (int)idx[v] >= L ? 0u : ~0u;
+}
+
 // Two ants per wave64 (1 <= cl <= 32): lanes 0-31 serve ant `ant0`, lanes
 // 32-63 ant `ant0 + 1` (absent if !hasB). Both take their candidate steps
 // together: lane 32h + r holds rank r of ant h's current row, the keys and
 // the per-half argmax are those of construct_ant. A step in which an ant has
 // no unvisited candidate runs that ant's fallback on the whole wave. Same
-// draws, same arithmetic, same tours as one ant per wave.
+// draws, same arithmetic, same tours as one ant per wave. Laid out like the
+// single colony's step: both current cities wave-uniform, draws generated
+// once per group of steps, the visited test folded into the key code.
 template <int kTabu, int kPher>
 __device__ void construct_pair(const Views& vw, const Shape& s, uint32_t it, int ant0, bool hasB, int lane,
                                uint8_t* regA, uint8_t* regB, const uint16_t* tcand, const float* tchc, int R) {
@@ -983,41 +1001,32 @@ __device__ void construct_pair(const Views& vw, const Shape& s, uint32_t it, int
     // start cities: floor(x * n / 2^32) of draw (step 0, slot 0) of each ant
     const uint32_t x0 = draw_block(seed, it, my_ant, 0u, 0u).w[0];
     const uint32_t st_l = (uint32_t)(((uint64_t)x0 * (uint64_t)n) >> 32);
-    const uint32_t startA = (uint32_t)__builtin_amdgcn_readlane((int)st_l, 0);
-    const uint32_t startB = (uint32_t)__builtin_amdgcn_readlane((int)st_l, 32);
-    tabA.mark(startA, lane);
-    if (hasB) tabB.mark(startB, lane ^ 32);
+    const int startA = __builtin_amdgcn_readlane((int)st_l, 0);
+    const int startB = __builtin_amdgcn_readlane((int)st_l, 32);
+    tabA.mark((uint32_t)startA, lane);
+    if (hasB) tabB.mark((uint32_t)startB, lane ^ 32);
 
     // draws ahead, S = 32/G steps at a time, each half for its own ant
     const int gsh = cl <= 4 ? 0 : cl <= 8 ? 1 : cl <= 16 ? 2 : 3;
     const int G = 1 << gsh;
     const int S = 32 >> gsh;
+    const int lr = hl < cl ? hl : cl - 1;
+    const uint32_t lane_ok = (hl < cl) & (h == 0 || hasB) ? ~0u : 0u;
+    const int ln_lane = hl & (4 * G - 1);
 
     uint16_t* tour_out = vw.tours + (size_t)my_ant * n;
     const int32_t* dist = vw.dist;
     const bool writer = h == 0 || hasB;
-    uint32_t tbuf = h ? startB : startA;  // lane 32h + (k & 31) holds the city of step k
+    uint32_t tbuf = (uint32_t)(h ? startB : startA);  // lane 32h + (k & 31) holds the city of step k
     uint32_t prev_last = 0;
     int64_t len = 0;
     int64_t fbA_steps = 0, fbA_nodes = 0, fbB_steps = 0, fbB_nodes = 0;
-    uint32_t curA = startA, curB = startB;
+    int curA = startA, curB = startB;
+    bool bad = false;
 
-    for (int k = 1; k < n; ++k) {
-        const uint32_t cur_l = h ? curB : curA;
-        const int e = (int)cur_l * cl + (hl < cl ? hl : cl - 1);
-        uint32_t node;
-        float w;
-        if ((int)cur_l < R) {
-            node = lds_cand[e];
-            w = lds_chc[e];
-        } else {
-            node = glb_cand[e];
-            w = glb_chc[e];
-        }
-        const int j = (k - 1) & (S - 1);
-        if (j == 0) {
-            const int ks = k + (hl >> gsh);
-            const Words4 b = draw_block(seed, it, my_ant, (uint32_t)ks, (uint32_t)(4 * (hl & (G - 1))));
+    for (int k0 = 0; k0 < n; k0 += S) {
+        {
+            const Words4 b = draw_block(seed, it, my_ant, (uint32_t)(k0 + (hl >> gsh)), (uint32_t)(4 * (hl & (G - 1))));
             float4 lv;
             lv.x = log_u01(u01(b.w[0]));
             lv.y = log_u01(u01(b.w[1]));
@@ -1025,62 +1034,81 @@ __device__ void construct_pair(const Views& vw, const Shape& s, uint32_t it, int
             lv.w = log_u01(u01(b.w[3]));
             *reinterpret_cast<float4*>(lnbuf + 4 * hl) = lv;
         }
-        const float lnu = lnbuf[4 * j * G + (hl & (4 * G - 1))];
-        float key = lnu * w;  // (w holds 1 / choice_info)
-        asm volatile("" : "+v"(key));  // every lane divides, overlapping the visited-bit load
-        const Tabu mine = h ? tabB : tabA;  // this half's tabu
-        const bool live = (hl < cl) & !mine.visited(node) & writer;
-        const uint32_t code = live ? ord_key(key) : 0u;
-        uint32_t bestA, bestB;
-        half_max_u32(code, bestA, bestB);
-        const uint32_t best_l = h ? bestB : bestA;
-        const uint64_t tied = __ballot(live && code == best_l);
-        const uint32_t tA = (uint32_t)tied, tB = (uint32_t)(tied >> 32);
-        uint32_t nextA = kNone, nextB = kNone;
-        if (__popc(tA) > 1 || __popc(tB) > 1) {
-            uint32_t mA, mB;
-            half_min_u32(((tied >> lane) & 1ull) ? node : kNone, mA, mB);
-            nextA = mA;
-            nextB = mB;
-        } else {
-            if (tA) nextA = (uint32_t)__builtin_amdgcn_readlane((int)node, __ffs(tA) - 1);
-            if (tB) nextB = (uint32_t)__builtin_amdgcn_readlane((int)node, 32 + __ffs(tB) - 1);
-        }
-        if (__builtin_expect(nextA == kNone, 0)) {
-            fbA_steps += 1;
-            fbA_nodes += n - k;
-            nextA = fallback_step<kTabu, kPher>(vw, s, it, antA, curA, k, tabA, regA, tmin_a, lane);
-        }
-        if (!hasB) {
-            nextB = curB;  // an absent second ant stays at its (valid) start city
-        } else if (__builtin_expect(nextB == kNone, 0)) {
-            fbB_steps += 1;
-            fbB_nodes += n - k;
-            nextB = fallback_step<kTabu, kPher>(vw, s, it, antB, curB, k, tabB, regB, tmin_a, lane);
-        }
-        if (nextA >= (uint32_t)n || nextB >= (uint32_t)n) {
-            if (lane == 0) atomicOr(&vw.state->flags, 8u);
-            break;
-        }
-        tabA.mark(nextA, lane);
-        if (hasB) tabB.mark(nextB, lane ^ 32);
-        const int slot = k & 31;
-        if (hl == slot) tbuf = h ? nextB : nextA;
-        curA = nextA;
-        curB = nextB;
-        if (slot == 31 || k == n - 1) {
-            const int k0 = k - slot;
-            const uint32_t prev = __shfl_up(tbuf, 1);
-            if (hl <= slot && writer) {
-                tour_out[k0 + hl] = (uint16_t)tbuf;
-                const uint32_t from = hl == 0 ? prev_last : prev;
-                if (k0 + hl > 0) len += dist[(size_t)from * n + tbuf];
+        const int kb = k0 > 0 ? k0 : 1;
+        const int ke = k0 + S < n ? k0 + S : n;
+        for (int k = kb; k < ke; ++k) {
+            const int cur_l = h ? curB : curA;
+            const int e = cur_l * cl + lr;
+            uint32_t node;
+            float w;
+            if (R == 0 || cur_l >= R) {
+                node = glb_cand[e];
+                w = glb_chc[e];
+            } else {
+                node = lds_cand[e];
+                w = lds_chc[e];
             }
-            const uint32_t plA = (uint32_t)__builtin_amdgcn_readlane((int)tbuf, slot);
-            const uint32_t plB = (uint32_t)__builtin_amdgcn_readlane((int)tbuf, 32 + slot);
+            const float lnu = lnbuf[4 * (k - k0) * G + ln_lane];
+            const uint32_t live = live_pair(tabA, tabB, h, node);
+            float key = lnu * w;  // (w holds 1 / choice_info)
+            asm volatile("" : "+v"(key));
+            // ln(u) < 0 and w >= 0: the key's sign bit is set, its order code is ~bits
+            const uint32_t code = ~__float_as_uint(key) & live & lane_ok;
+            uint32_t bestA, bestB;
+            half_max_u32(code, bestA, bestB);
+            const uint32_t best_l = h ? bestB : bestA;
+            const uint64_t tied = __ballot(code == best_l);
+            const uint32_t tA = (uint32_t)tied, tB = (uint32_t)(tied >> 32);
+            uint32_t nextA = kNone, nextB = kNone;
+            if (bestA) nextA = (uint32_t)__builtin_amdgcn_readlane((int)node, __builtin_ctz(tA));
+            if (bestB) nextB = (uint32_t)__builtin_amdgcn_readlane((int)node, 32 + __builtin_ctz(tB));
+            if (__builtin_expect(((tA & (tA - 1)) | (tB & (tB - 1))) != 0, 0)) {
+                uint32_t mA, mB;
+                half_min_u32(((tied >> lane) & 1ull) ? node : kNone, mA, mB);
+                if (bestA) nextA = mA;
+                if (bestB) nextB = mB;
+            }
+            if (__builtin_expect(nextA == kNone, 0)) {
+                fbA_steps += 1;
+                fbA_nodes += n - k;
+                nextA = (uint32_t)__builtin_amdgcn_readfirstlane(
+                    (int)fallback_step<kTabu, kPher>(vw, s, it, antA, (uint32_t)curA, k, tabA, regA, tmin_a, lane));
+            }
+            if (!hasB) {
+                nextB = (uint32_t)curB;  // an absent second ant stays at its (valid) start city
+            } else if (__builtin_expect(nextB == kNone, 0)) {
+                fbB_steps += 1;
+                fbB_nodes += n - k;
+                nextB = (uint32_t)__builtin_amdgcn_readfirstlane(
+                    (int)fallback_step<kTabu, kPher>(vw, s, it, antB, (uint32_t)curB, k, tabB, regB, tmin_a, lane));
+            }
+            // no city is unreachable with a validated instance; were it not,
+            // report it after the tour and go on with city 0 (the tour is void)
+            bad |= (nextA >= (uint32_t)n) | (nextB >= (uint32_t)n);
+            nextA = nextA < (uint32_t)n ? nextA : 0u;
+            nextB = nextB < (uint32_t)n ? nextB : 0u;
+            tabA.mark(nextA, lane);
+            if (hasB) tabB.mark(nextB, lane ^ 32);
+            if (hl == (k & 31)) tbuf = h ? nextB : nextA;
+            curA = __builtin_amdgcn_readfirstlane((int)nextA);
+            curB = __builtin_amdgcn_readfirstlane((int)nextB);
+        }
+        if ((ke & 31) == 0 || ke == n) {
+            // flush steps c0 .. ke - 1; lane 32h + l holds step c0 + l of ant h
+            const int c0 = (ke - 1) & ~31;
+            const int last = ke - 1 - c0;
+            const uint32_t prev = __shfl_up(tbuf, 1);
+            if (hl <= last && writer) {
+                tour_out[c0 + hl] = (uint16_t)tbuf;
+                const uint32_t from = hl == 0 ? prev_last : prev;
+                if (c0 + hl > 0) len += dist[(size_t)from * n + tbuf];
+            }
+            const uint32_t plA = (uint32_t)__builtin_amdgcn_readlane((int)tbuf, last);
+            const uint32_t plB = (uint32_t)__builtin_amdgcn_readlane((int)tbuf, 32 + last);
             prev_last = h ? plB : plA;
         }
     }
+    if (bad && lane == 0) atomicOr(&vw.state->flags, 8u);
     if (lane == 0) len += dist[(size_t)curA * n + startA];  // closing edges
     if (lane == 32 && hasB) len += dist[(size_t)curB * n + startB];
     for (int o = 16; o >= 1; o >>= 1) len += __shfl_xor(len, o);
