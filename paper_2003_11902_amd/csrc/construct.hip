@@ -762,20 +762,28 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
         cur = __builtin_amdgcn_readfirstlane((int)next);
     };
 
-    // One candidate-phase step k reading its draws at lnbuf[4jG + r]; `mid`
-    // runs between the row loads and their first use (independent work that
-    // fills their latency).
-    auto cand_step = [&](int k, int j, auto&& mid) {
-        const int e = cur * cl + lr;
-        uint32_t node;
-        float w;
-        if (__builtin_expect(cur < R, 1)) {
-            node = lds_cand[e];
-            w = lds_chc[e];
+    // The row entry of this lane for city c (rank lr of its candidate list),
+    // loaded one step ahead: as soon as the next city is known, before it is
+    // marked, so the loads are not queued behind the mark.
+    uint32_t node_next = 0;
+    float w_next = 0.0f;
+    auto load_row = [&](int c) {
+        const int e = c * cl + lr;
+        if (__builtin_expect(c < R, 1)) {
+            node_next = lds_cand[e];
+            w_next = lds_chc[e];
         } else {
-            node = glb_cand[e];
-            w = glb_chc[e];
+            node_next = glb_cand[e];
+            w_next = glb_chc[e];
         }
+    };
+
+    // One candidate-phase step k reading its draws at lnbuf[4jG + r] and the
+    // row loaded ahead for the current city; `mid` runs before the row's
+    // first use (independent work that fills the loads' latency).
+    auto cand_step = [&](int k, int j, auto&& mid) {
+        const uint32_t node = node_next;
+        const float w = w_next;
         mid();
         const float lnu = lds_ln[4 * j * G + ln_lane];
         const uint32_t live = tabu.live(node);
@@ -794,6 +802,7 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
                 next = wave_min_u32<kRows>(code == best ? node : kNone);
         }
         if (__builtin_expect(next == kNone, 0)) next = fallback(k);
+        load_row((int)next);
         advance(next, k);
     };
 
@@ -838,6 +847,7 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
             flush(k + 1);
         }
     } else if constexpr (kG > 0) {
+        load_row(cur);
         // Draws computed one group ahead, spread over the steps of the group
         // before in seven pieces (three of Philox rounds, the last round with
         // the first logarithm, one logarithm each) that fill the latency of
@@ -892,6 +902,7 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
             flush(n);
         }
     } else {
+        load_row(cur);
         for (int k0 = 0; k0 < n; k0 += S) {
             draws_now(k0);
             const int ke = k0 + S < n ? k0 + S : n;

@@ -58,11 +58,12 @@ __device__ __forceinline__ Words4 draw_block(uint64_t seed, uint32_t it, uint32_
 }
 
 __device__ __forceinline__ uint32_t pick_word(const Words4& b, uint32_t idx) {
-    // idx in 0..3; masks instead of an indexed array so the words stay in
-    // registers
-    const uint32_t m0 = 0u - (uint32_t)(idx == 0u), m1 = 0u - (uint32_t)(idx == 1u);
-    const uint32_t m2 = 0u - (uint32_t)(idx == 2u), m3 = 0u - (uint32_t)(idx == 3u);
-    return (b.w[0] & m0) | (b.w[1] & m1) | (b.w[2] & m2) | (b.w[3] & m3);
+    // idx in 0..3: a two-level select on its bits (the words stay in
+    // registers; three selects and two bit tests)
+    const bool lo = (idx & 1u) != 0u, hi = (idx & 2u) != 0u;
+    const uint32_t w01 = lo ? b.w[1] : b.w[0];
+    const uint32_t w23 = lo ? b.w[3] : b.w[2];
+    return hi ? w23 : w01;
 }
 
 // u = (2 * (x >> 9) + 1) * 2^-24: exact, strictly inside (0, 1).
