@@ -203,8 +203,9 @@ mmas_status mmas_two_opt(mmas_ctx* ctx);
 
 /* Launch shape of the 2-opt kernel; results never depend on it.
  * `waves_per_ant`: wave64s of the workgroup that runs one ant's search, 1, 2,
- * 4, 8 or 16 (0 = default 4); each round examines threads / (2*ls_nn
- * rounded up to a power of two) cities. EINVAL for other values. */
+ * 4, 8 or 16 (0 = by the instance: 4 below 1024 cities, 8 below 8192, 16
+ * from there); each round examines min(64, threads / (2*ls_nn rounded up to
+ * a power of two)) cities. EINVAL for other values. */
 mmas_status mmas_set_two_opt_launch(mmas_ctx* ctx, int32_t waves_per_ant);
 
 /* The end of an iteration of Alg. 1: the iteration best (shortest tour,

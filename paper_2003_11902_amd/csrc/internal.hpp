@@ -52,7 +52,7 @@ struct Shape {
     int table_rows;      // rows of the candidate table staged in LDS (-1: all that fit)
     int list_cap;        // construction: entries of a bitmask fallback's city list
                          // (0: min(n, kListCap); the launcher may raise it to n)
-    int two_opt_waves;   // 2-opt launch: waves per ant (1..16)
+    int two_opt_waves;   // 2-opt launch: waves per ant (1..16; 0: by the instance size)
 };
 
 // One instance of a batch (device array, one entry per instance).

@@ -82,7 +82,7 @@ Shape shape_of(const mmas_params* p) {
     s.table_rows = -1;
     s.lanes_per_ant = 64;
     s.construct_waves = 0;
-    s.two_opt_waves = 4;
+    s.two_opt_waves = 0;  // by the instance size (launch_two_opt)
     return s;
 }
 
@@ -345,7 +345,7 @@ mmas_status mmas_set_two_opt_launch(mmas_ctx* c, int32_t waves_per_ant) {
     if (waves_per_ant != 0 && waves_per_ant != 1 && waves_per_ant != 2 && waves_per_ant != 4 && waves_per_ant != 8 &&
         waves_per_ant != 16)
         return MMAS_EINVAL;
-    c->s.two_opt_waves = waves_per_ant == 0 ? 4 : waves_per_ant;
+    c->s.two_opt_waves = waves_per_ant;
     return MMAS_OK;
 }
 

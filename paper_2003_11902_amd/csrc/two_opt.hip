@@ -20,21 +20,19 @@
 namespace mmas {
 namespace {
 
-__device__ __forceinline__ int64_t dd(const int32_t* dist, int n, uint32_t x, uint32_t y) {
-    return (int64_t)dist[(size_t)x * n + y];
-}
-
 constexpr int kMaxWaves = 16;
-constexpr int kMaxList = 512;  // cities examined per round (1024 threads / groups of >= 2)
+constexpr int kListCap = 64;  // list entries kept, one per lane of the first wave
 
-struct Cand {
-    int key;                 // (list index << 6) | lane in group
+// A wave's first move: its end points, their positions, the new edges'
+// lengths; flags bit 0 = predecessor direction, bits 1-3 = don't-look bits
+// of a1, c, c1 before the round.
+struct Move {
     int a, a1, c, c1;
-    int i, j;                // cyclic position range to reverse
-    int dac, da1c1;          // lengths of the two new edges
-    int flags;               // bits 0-3: don't-look bit of a, a1, c, c1 before the round;
-                             // bit 4: the edge left of position i becomes {a, c}
+    int pa, pc;
+    int dac, da1c1;
+    int flags;
 };
+constexpr uint32_t kNoMove = 0xFFFFFFFFu;
 
 __device__ __forceinline__ uint32_t dlb_bit(const uint32_t* dlb, int x) { return (dlb[x >> 5] >> (x & 31)) & 1u; }
 
@@ -81,27 +79,38 @@ __device__ void list_active(const uint32_t* dlb, int words, uint32_t lastmask, i
 // in LDS by position (len[p] = d(tour[p], tour[p+1])), so a move evaluation
 // reads one distance from HBM instead of three.
 //
-// A round examines the next C active cities in cyclic index order (C =
-// threads / group, a group of 2k lanes per city) against the current tour.
-// The first of them (in that order) with an improving move is the city the
-// sequential search reaches next with a move: the cities before it have none
-// and get their bits set, its move is applied and it is examined again. With
-// no move among the C, all C get their bits set. The number of active cities
-// and the cursor are kept by every thread alike (no broadcast needed).
+// A round examines the first E entries of a list of the next active cities
+// in cyclic index order (E = threads / group, a group of 2k lanes per city,
+// at most 64) against the current tour. The first of them (in that order)
+// with an improving move is the city the sequential search reaches next with
+// a move: the cities before it have none and get their bits set, its move is
+// applied and it is examined again. Without a move all E get their bits set.
+// Any prefix of the active cities in cyclic order from the cursor serves as
+// the list, so the next list is the old one from the move's city (or from
+// the first city not examined) on, with the end points that became active
+// inside its range merged in; the don't-look bits are scanned again only
+// when that list gets short. The first wave keeps the list (one entry per
+// lane), the bits, the cursor and the count of active cities; the others
+// reverse the path meanwhile.
 template <bool kLen>
 __global__ __launch_bounds__(1024) void k_two_opt(Views vw, Shape s, const int32_t* __restrict__ nnd) {
     extern __shared__ __align__(16) uint8_t smem[];
-    __shared__ uint16_t s_lists[2][kMaxList];  // by round parity
-    __shared__ Cand s_cand[kMaxWaves];
-    __shared__ int s_key[kMaxWaves];
+    __shared__ uint16_t s_lists[2][kListCap];  // by round parity
+    __shared__ int s_count[2];                  // entries of each list (0: the search has ended)
+    __shared__ uint32_t s_best[2];              // lowest thread (list index, lane in group) with a move
+    __shared__ Move s_mv[kMaxWaves];            // each wave's first move
     __shared__ unsigned long long s_len;
     const int n = s.n, k = s.ls_nn;
     const int ant = blockIdx.x;
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int t = threadIdx.x, lane = t & 63;
+    // wave-uniform values are read into scalar registers (readfirstlane), so
+    // that the bookkeeping of a round takes scalar branches
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int nthr = blockDim.x, nwaves = nthr >> 6;
     int gs = 1;
     while (gs < 2 * k) gs <<= 1;  // lanes per city (power of two <= 64)
-    const int C = min(nthr / gs, kMaxList);
+    const int lg = __builtin_ctz(gs);
+    const int E = min(nthr >> lg, kListCap);  // cities examined per round
     uint16_t* tour = reinterpret_cast<uint16_t*>(smem);
     uint16_t* pos = tour + n;
     const size_t tp_bytes = (4 * (size_t)n + 15) & ~(size_t)15;
@@ -121,34 +130,53 @@ __global__ __launch_bounds__(1024) void k_two_opt(Views vw, Shape s, const int32
         pos[v] = (uint16_t)i;
     }
     for (int w = t; w < words; w += nthr) dlb[w] = 0u;
-    if (t == 0) s_len = 0ull;
+    if (t == 0) {
+        s_len = 0ull;
+        s_best[0] = s_best[1] = kNoMove;
+    }
     __syncthreads();
     if (kLen)
         for (int i = t; i < n; i += nthr) elen[i] = dist[(size_t)tour[i] * n + tour[i + 1 == n ? 0 : i + 1]];
 
-    int act = n, a0 = 0;  // active cities and cursor (the same in every thread)
+    // Roles after a round's move is known: wave 0 sets and clears the
+    // don't-look bits and tops the next list up from them, wave 1 merges the
+    // next list from the current one, the other waves reverse the path (with
+    // fewer waves, wave 0 also merges, and a single wave does everything).
+    const int merge_wave = nwaves > 2 ? 1 : 0;
+    const int rev_wave0 = nwaves > 2 ? 2 : nwaves - 1;
+    int act = n, a0 = 0;            // active cities, cursor (kept alike by the first two waves)
     int ca = -1, cc = 0, cdac = 0;  // this lane's last (city, neighbour, distance) from the lists
+    // a list shorter than this is topped up from the bits
+    const int refill = min(E, 8);
     // every round sets a bit or shortens the tour; the cap only guards
     // against a search that would not end
     const long long max_rounds = 256ll * n + 4096;
     long long rounds = 0;
-    if (wave == 0) list_active(dlb, words, lastmask, 0, min(C, n), s_lists[1], lane);
-    while (act > 0) {
-        if (++rounds > max_rounds) {
+    if (wave == 0) {
+        list_active(dlb, words, lastmask, 0, min(kListCap, n), s_lists[1], lane);
+        if (lane == 0) s_count[1] = min(kListCap, n);
+    }
+    for (;;) {
+        ++rounds;
+        const int par = (int)(rounds & 1);
+        const uint16_t* s_list = s_lists[par];
+
+        __syncthreads();  // the list, the tour, positions, lengths and bits of this round
+        const int count = __builtin_amdgcn_readfirstlane(s_count[par]);
+        if (count == 0) break;
+        if (rounds > max_rounds) {
             if (t == 0) atomicOr(&vw.state->flags, 16u);
             return;
         }
-        const int count = min(C, act);
-        uint16_t* s_list = s_lists[rounds & 1];  // listed by wave 0 at the end of the last round
+        const int ev = min(count, E);
+        const int le = (wave <= merge_wave && lane < count) ? (int)s_list[lane] : 0;  // the list, one entry a lane
 
-        __syncthreads();  // the list, the tour, positions, lengths and bits of this round
-
-        // ---- evaluate every candidate move of the listed cities ----
-        const int g = t / gs, rl = t % gs;
-        bool ok = false;
-        int a = 0, a1 = 0, c = 0, c1 = 0, dac = 0, da1c1 = 0, pa = 0, pc = 0;
+        // ---- evaluate every candidate move of the first ev listed cities ----
+        const int g = t >> lg, rl = t & (gs - 1);
         const bool pred_dir = rl >= k;
-        if (g < count && rl < 2 * k) {
+        bool ok = false;
+        int a = 0, a1 = 0, c = 0, c1 = 0, dac = 0, da1c1 = 0, pa = 0, pc = 0, fl = 0;
+        if (g < ev && rl < 2 * k) {
             a = s_list[g];
             const int r = pred_dir ? rl - k : rl;
             if (a != ca) {  // the list often starts where the last one did
@@ -158,111 +186,135 @@ __global__ __launch_bounds__(1024) void k_two_opt(Views vw, Shape s, const int32
             }
             c = cc;
             dac = cdac;
+            // both ends' positions, then both tour neighbours and edge lengths
             pa = pos[a];
+            pc = pos[c];
             const int pa_n = pa + 1 == n ? 0 : pa + 1, pa_p = pa == 0 ? n - 1 : pa - 1;
-            a1 = pred_dir ? tour[pa_p] : tour[pa_n];
-            const int32_t daa1 = kLen ? elen[pred_dir ? pa_p : pa] : dist[(size_t)a * n + a1];
-            const int64_t g1 = (int64_t)daa1 - dac;
-            if (g1 > 0) {
-                pc = pos[c];
-                const int pc_n = pc + 1 == n ? 0 : pc + 1, pc_p = pc == 0 ? n - 1 : pc - 1;
-                c1 = pred_dir ? tour[pc_p] : tour[pc_n];
-                if (c != a1 && c1 != a) {
-                    const int32_t dcc1 = kLen ? elen[pred_dir ? pc_p : pc] : dist[(size_t)c * n + c1];
-                    da1c1 = dist[(size_t)a1 * n + c1];
-                    ok = g1 + (int64_t)dcc1 - (int64_t)da1c1 > 0;
-                }
+            const int pc_n = pc + 1 == n ? 0 : pc + 1, pc_p = pc == 0 ? n - 1 : pc - 1;
+            a1 = tour[pred_dir ? pa_p : pa_n];
+            c1 = tour[pred_dir ? pc_p : pc_n];
+            const int64_t daa1 = kLen ? (int64_t)elen[pred_dir ? pa_p : pa] : (int64_t)dist[(size_t)a * n + a1];
+            const int64_t g1 = daa1 - dac;
+            if (g1 > 0 && c != a1 && c1 != a) {
+                const int32_t dcc1 = kLen ? elen[pred_dir ? pc_p : pc] : dist[(size_t)c * n + c1];
+                da1c1 = dist[(size_t)a1 * n + c1];
+                // the end points' don't-look bits, read while the distance loads
+                fl = (pred_dir ? 1 : 0) | ((int)dlb_bit(dlb, a1) << 1) | ((int)dlb_bit(dlb, c) << 2) |
+                     ((int)dlb_bit(dlb, c1) << 3);
+                ok = g1 + (int64_t)dcc1 - (int64_t)da1c1 > 0;
             }
         }
         const uint64_t mask = __ballot(ok);
-        if (mask != 0ull) {
-            const int m = __ffsll((unsigned long long)mask) - 1;  // lowest lane: first city, first move
-            if (lane == m) {
-                // the two paths the move may reverse (positions from pa and pc:
-                // a1 and c1 sit next to a and c); the shorter one, the first on a tie
-                const int pa_n = pa + 1 == n ? 0 : pa + 1, pa_p = pa == 0 ? n - 1 : pa - 1;
-                const int pc_n = pc + 1 == n ? 0 : pc + 1, pc_p = pc == 0 ? n - 1 : pc - 1;
-                int i1, j1, i2, j2;
-                if (!pred_dir) {  // a -> a1 ... c -> c1: a1..c or c1..a
-                    i1 = pa_n;
-                    j1 = pc;
-                    i2 = pc_n;
-                    j2 = pa;
-                } else {          // a1 -> a ... c1 -> c: a..c1 or c..a1
-                    i1 = pa;
-                    j1 = pc_p;
-                    i2 = pc;
-                    j2 = pa_p;
-                }
-                int len1 = j1 - i1;
-                if (len1 < 0) len1 += n;
-                len1 += 1;
-                const bool first = len1 <= n - len1;
-                const int i = first ? i1 : i2, j = first ? j1 : j2;
-                const int x = tour[i == 0 ? n - 1 : i - 1];  // stays left of the reversed path
-                const int fl = (int)dlb_bit(dlb, a) | ((int)dlb_bit(dlb, a1) << 1) | ((int)dlb_bit(dlb, c) << 2) |
-                               ((int)dlb_bit(dlb, c1) << 3) | ((x == a || x == c) ? 16 : 0);
-                s_cand[wave] = Cand{(g << 6) | rl, a, a1, c, c1, i, j, dac, da1c1, fl};
-                s_key[wave] = (g << 6) | rl;
-            }
-        } else if (lane == 0) {
-            s_key[wave] = 0x7FFFFFFF;
+        if (mask != 0ull && lane == __ffsll((unsigned long long)mask) - 1) {
+            // lowest lane: first city, first move of this wave
+            s_mv[wave] = Move{a, a1, c, c1, pa, pc, dac, da1c1, fl};
+            atomicMin(&s_best[par], (uint32_t)t);  // thread index: list index, then lane in group
         }
         __syncthreads();
-        // the first move over all waves: keys are (list index, lane), distinct
-        const uint32_t kk = lane < nwaves ? (uint32_t)s_key[lane] : 0x7FFFFFFFu;
-        const uint32_t kmin = wave_min_u32<2>(kk);  // lanes 0-31 (kMaxWaves <= 32)
-        const int best = __ffsll((unsigned long long)__ballot(kk == kmin)) - 1;
-        const bool moved = kmin != 0x7FFFFFFFu;
-        Cand mv{};
-        if (moved) mv = s_cand[best];
-        const int gstar = moved ? (mv.key >> 6) : count;  // the listed cities before it have no move
-        const int last = s_list[count - 1];
-        int newact = act - gstar;
-        const int ends[4] = {mv.a, mv.a1, mv.c, mv.c1};
+        // the first move over all waves
+        const uint32_t best = __builtin_amdgcn_readfirstlane(s_best[par]);
+        const bool moved = best != kNoMove;
+        Move mv{};
         if (moved) {
-            // an end point's bit is set after the listing if it was set before
-            // the round or if it lies in the listed part before the move's city
-            int span = mv.a - a0;
-            if (span < 0) span += n;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                int de = ends[e] - a0;
-                if (de < 0) de += n;
-                const bool was = ((mv.flags >> e) & 1) || (e > 0 && de < span);
-                newact += was ? 1 : 0;
-            }
+            const Move m = s_mv[best >> 6];
+            mv = Move{__builtin_amdgcn_readfirstlane(m.a),   __builtin_amdgcn_readfirstlane(m.a1),
+                      __builtin_amdgcn_readfirstlane(m.c),   __builtin_amdgcn_readfirstlane(m.c1),
+                      __builtin_amdgcn_readfirstlane(m.pa),  __builtin_amdgcn_readfirstlane(m.pc),
+                      __builtin_amdgcn_readfirstlane(m.dac), __builtin_amdgcn_readfirstlane(m.da1c1),
+                      __builtin_amdgcn_readfirstlane(m.flags)};
         }
-        const int a0_next = moved ? mv.a : (last + 1 == n ? 0 : last + 1);
-        // Wave 0 owns the don't-look bits: the listed cities before the move's
-        // city get theirs set (except the move's end points, whose bits end
-        // clear), the end points' are cleared, and the next round's cities
-        // are listed while the other waves reverse the path.
-        if (wave == 0) {
-            for (int q = lane; q < gstar; q += kWave) {
-                const int x = s_list[q];
-                if (!moved || (x != mv.a1 && x != mv.c && x != mv.c1))
-                    atomicOr(&dlb[x >> 5], 1u << (x & 31));
+        const int gstar = moved ? (int)(best >> lg) : ev;  // the listed cities before it have no move
+
+        if (wave <= merge_wave) {
+            const int last = __builtin_amdgcn_readlane(le, count - 1);
+            auto cyc = [&](int x) { return x >= a0 ? x - a0 : x - a0 + n; };
+            // The end points a1, c, c1: their don't-look bits before the
+            // round (w), cyclic places (q), and the places of those merged
+            // into the next list (inactive before, inside (a, last]; n for
+            // the others). Everything here is wave-uniform but the lists.
+            const int e1 = mv.a1, e2 = mv.c, e3 = mv.c1;
+            const int w1 = (mv.flags >> 1) & 1, w2 = (mv.flags >> 2) & 1, w3 = (mv.flags >> 3) & 1;
+            const int qa = cyc(mv.a), ql = cyc(last), q1 = cyc(e1), q2 = cyc(e2), q3 = cyc(e3);
+            const int m1 = moved && w1 && q1 > qa && q1 <= ql ? q1 : n;
+            const int m2 = moved && w2 && q2 > qa && q2 <= ql ? q2 : n;
+            const int m3 = moved && w3 && q3 > qa && q3 <= ql ? q3 : n;
+            // the listed cities before the move's city lose their bits (except
+            // end points); the end points are all active afterwards: those
+            // inactive before, and those listed before the move's city, count
+            // again
+            const int newact = act - gstar +
+                               (moved ? (int)(w1 | (q1 < qa)) + (int)(w2 | (q2 < qa)) + (int)(w3 | (q3 < qa)) : 0);
+            const int ee = lane == 0 ? e1 : lane == 1 ? e2 : e3;
+            const int cap = min(kListCap, newact);
+            // kept: the move's city (first) and the entries after it, or the
+            // entries not examined; merged end points in cyclic order
+            const int keep0 = moved ? gstar + 1 : gstar, head = moved ? 1 : 0;
+            const int merged = (int)(m1 < n) + (int)(m2 < n) + (int)(m3 < n);
+            int len = newact > 0 ? min(cap, head + count - keep0 + merged) : 0;
+            uint16_t* nl = s_lists[par ^ 1];
+            if (wave == 0) {
+                if (lane == 0) s_best[par ^ 1] = kNoMove;  // for the next round
+                const bool is_end = moved && (le == e1 || le == e2 || le == e3);
+                if (lane < gstar && !is_end) atomicOr(&dlb[le >> 5], 1u << (le & 31));
+                const int we = lane == 0 ? w1 : lane == 1 ? w2 : w3;
+                if (moved && lane < 3 && we) atomicAnd(&dlb[ee >> 5], ~(1u << (ee & 31)));
             }
-            if (moved && lane < 4 && ((mv.flags >> lane) & 1))
-                atomicAnd(&dlb[ends[lane] >> 5], ~(1u << (ends[lane] & 31)));
-            if (newact > 0)
-                list_active(dlb, words, lastmask, a0_next, min(C, newact), s_lists[(rounds + 1) & 1], lane);
+            if (wave == merge_wave && newact > 0) {
+                const bool keep = lane >= keep0 && lane < count;
+                const int cx = cyc(le);
+                const int idx = head + lane - keep0 + (int)(m1 < cx) + (int)(m2 < cx) + (int)(m3 < cx);
+                if (keep && idx < cap) nl[idx] = (uint16_t)le;
+                // lanes 0-2: the place of merged end point e1, e2, e3 (lane 0
+                // first writes the move's city)
+                const int r1 = __popcll(__ballot(keep && cx < m1));
+                const int r2 = __popcll(__ballot(keep && cx < m2));
+                const int r3 = __popcll(__ballot(keep && cx < m3));
+                const int mm = lane == 0 ? m1 : lane == 1 ? m2 : m3;
+                const int rr = lane == 0 ? r1 : lane == 1 ? r2 : r3;
+                const int ie = head + rr + (int)(m1 < mm) + (int)(m2 < mm) + (int)(m3 < mm);
+                if (moved && lane == 0) nl[0] = (uint16_t)mv.a;
+                if (lane < 3 && mm < n && ie < cap) nl[ie] = (uint16_t)ee;
+            }
+            int a0n = last + 1 == n ? 0 : last + 1;
+            if (len > 0) a0n = moved ? mv.a : __builtin_amdgcn_readlane(le, gstar);
+            if (len < cap && len < refill) {
+                // the next active cities after the last listed one (after the
+                // bits above: wave 0's own LDS operations complete in order)
+                if (wave == 0)
+                    list_active(dlb, words, lastmask, last + 1 == n ? 0 : last + 1, cap - len, nl + len, lane);
+                len = cap;
+            }
+            if (wave == 0 && lane == 0) s_count[par ^ 1] = len;
+            a0 = a0n;
+            act = newact;
         }
-        if (moved && (wave > 0 || nwaves == 1)) {
+        if (moved && wave >= rev_wave0) {
+            // the two paths the move may reverse (a1 and c1 sit next to a and
+            // c); the shorter one, the first on a tie
+            const bool pd = mv.flags & 1;
+            const int pa_n = mv.pa + 1 == n ? 0 : mv.pa + 1, pa_p = mv.pa == 0 ? n - 1 : mv.pa - 1;
+            const int pc_n = mv.pc + 1 == n ? 0 : mv.pc + 1, pc_p = mv.pc == 0 ? n - 1 : mv.pc - 1;
+            const int i1 = pd ? mv.pa : pa_n, j1 = pd ? pc_p : mv.pc;  // a1..c or a..c1
+            const int i2 = pd ? mv.pc : pc_n, j2 = pd ? pa_p : mv.pa;  // c1..a or c..a1
+            int len1 = j1 - i1;
+            if (len1 < 0) len1 += n;
+            len1 += 1;
+            const bool first = len1 <= n - len1;
+            const int mi = first ? i1 : i2, mj = first ? j1 : j2;
             // reverse positions i..j of the tour and i..j-1 of the edge lengths:
             // pair q swaps tour[i+q] and tour[j-q], and elen[i+q] and
             // elen[j-1-q] (for even lengths the middle pair of the lengths is
             // one cell swapped with itself)
-            const int rt = nwaves == 1 ? t : t - kWave, rthr = nwaves == 1 ? nthr : nthr - kWave;
-            int len = mv.j - mv.i;
-            if (len < 0) len += n;
-            len += 1;
-            const int half = len / 2;
+            const int rt = t - rev_wave0 * kWave, rthr = nthr - rev_wave0 * kWave;
+            const int half = (first ? len1 : n - len1) / 2;
+            // position i - 1 lies outside the reversed path (at most n / 2 long)
+            const int pl = mi == 0 ? n - 1 : mi - 1;
+            int x = 0;
+            if (kLen && rt == 0) x = tour[pl];
             for (int q = rt; q < half; q += rthr) {
-                int p = mv.i + q;
+                int p = mi + q;
                 if (p >= n) p -= n;
-                int r = mv.j - q;
+                int r = mj - q;
                 if (r < 0) r += n;
                 int r1 = r - 1;
                 if (r1 < 0) r1 += n;
@@ -281,15 +333,14 @@ __global__ __launch_bounds__(1024) void k_two_opt(Views vw, Shape s, const int32
                     elen[r1] = ep;
                 }
             }
-            if (kLen && rt == 0) {  // the two new edges close the reversed path
-                const int pl = mv.i == 0 ? n - 1 : mv.i - 1;
-                const bool left_ac = (mv.flags >> 4) & 1;
+            if (kLen && rt == 0) {
+                // the two new edges close the reversed path: {a, c} and
+                // {a1, c1}, the one next to the city left of it first
+                const bool left_ac = x == mv.a || x == mv.c;
                 elen[pl] = left_ac ? mv.dac : mv.da1c1;
-                elen[mv.j] = left_ac ? mv.da1c1 : mv.dac;
+                elen[mj] = left_ac ? mv.da1c1 : mv.dac;
             }
         }
-        a0 = a0_next;
-        act = newact;
     }
     __syncthreads();
     // write back; the tour length from the final edges
@@ -341,7 +392,10 @@ hipError_t launch_two_opt(const Views& v, const Shape& s, const int32_t* nnd, hi
     Views vv = v;
     Shape ss = s;
     void* args[] = {(void*)&vv, (void*)&ss, (void*)&nnd};
-    return hipLaunchKernel(kern, dim3(s.ants), dim3(64 * s.two_opt_waves), args, lds, st);
+    // more waves shorten the reversal of long paths and cost a little more
+    // at the barriers: 4 below 1024 cities, 8 below 8192, 16 from there
+    const int waves = s.two_opt_waves ? s.two_opt_waves : s.n < 1024 ? 4 : s.n < 8192 ? 8 : 16;
+    return hipLaunchKernel(kern, dim3(s.ants), dim3(64 * waves), args, lds, st);
 }
 
 }  // namespace mmas
