@@ -148,8 +148,10 @@ mmas_status mmas_create(const int32_t* dist_host, const mmas_params* p, void* de
                         size_t ws_bytes, void* hip_stream, mmas_ctx** out);
 
 /* choice_info = tau^alpha * eta^beta in FP32 (Sec. 2.1), dense and along the
- * candidate lists. The pheromone update refreshes it as it writes tau, so this
- * launches only when tau changed in another way (set-up, mmas_set_pheromone). */
+ * candidate lists, with its reciprocal 1/choice_info beside both (the keys'
+ * factor, Sec. 4.2.2; internal to the workspace). The pheromone update
+ * refreshes both as it writes tau, so this launches only when tau changed in
+ * another way (set-up, mmas_set_pheromone). */
 mmas_status mmas_prepare_choice_info(mmas_ctx* ctx);
 
 /* Tour construction for iteration `iteration` (the inner loops of Alg. 1):

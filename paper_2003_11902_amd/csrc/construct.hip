@@ -132,6 +132,26 @@ struct ListTabu {
 
 // ---- fallback weights --------------------------------------------------------
 
+// A fallback key is ln(u) times the reciprocal of the weight (Sec. 4.2.2).
+// The factor functors give that reciprocal: read from the dense matrix of
+// reciprocals the update writes, or computed from the distance (trails kept
+// along the candidate lists only: every other weight is tau_min^alpha *
+// eta^beta).
+struct DenseFactor {
+    const float* row_inv;
+    __device__ __forceinline__ float operator()(uint32_t v) const { return row_inv[v]; }
+};
+
+struct CandFactor {
+    const int32_t* drow;
+    float tmin_a;
+    int beta;
+    __device__ __forceinline__ float operator()(uint32_t v) const {
+        return 1.0f / (tmin_a * heur_from_dist(drow[v], beta));
+    }
+};
+
+// The weights themselves (the roulette wheel sums them).
 struct DenseWeight {
     const float* row;
     __device__ __forceinline__ float operator()(uint32_t v) const { return row[v]; }
@@ -173,26 +193,26 @@ __device__ __forceinline__ void keep_best(uint32_t code, uint32_t node, uint32_t
 // per round and issues their weight loads before the Philox and logarithm
 // work, so the loads overlap it. Folds the best (code, city) of each lane
 // into bcode / bnode.
-template <class W>
-__device__ __forceinline__ void fallback_keys(const uint16_t* list, int L, const W& weight, int cl, uint64_t seed,
+template <class F>
+__device__ __forceinline__ void fallback_keys(const uint16_t* list, int L, const F& factor, int cl, uint64_t seed,
                                               uint32_t it, uint32_t ant, uint32_t step, int lane, uint32_t& bcode,
                                               uint32_t& bnode) {
     for (int base = 0; base < L; base += 4 * kWave) {
         uint32_t v[4];
-        float w[4];
+        float f[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int i = base + u * kWave + lane;
             v[u] = i < L ? (uint32_t)list[i] : kNone;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) w[u] = v[u] != kNone ? weight(v[u]) : 1.0f;
+        for (int u = 0; u < 4; ++u) f[u] = v[u] != kNone ? factor(v[u]) : 1.0f;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if (v[u] == kNone) continue;
             const uint32_t slot = (uint32_t)cl + v[u];
             const Words4 blk = draw_block(seed, it, ant, step, slot);
-            const float key = log_u01(u01(pick_word(blk, slot & 3u))) * (1.0f / w[u]);
+            const float key = log_u01(u01(pick_word(blk, slot & 3u))) * f[u];
             keep_best(ord_key(key), v[u], bcode, bnode);
         }
     }
@@ -200,11 +220,11 @@ __device__ __forceinline__ void fallback_keys(const uint16_t* list, int L, const
 
 // All-node fallback over a list of the L unvisited cities (the compact tabu's
 // left part).
-template <class W>
-__device__ __forceinline__ uint32_t fallback_list(const uint16_t* list, int L, const W& weight, int cl, uint64_t seed,
+template <class F>
+__device__ __forceinline__ uint32_t fallback_list(const uint16_t* list, int L, const F& factor, int cl, uint64_t seed,
                                                   uint32_t it, uint32_t ant, uint32_t step, int lane) {
     uint32_t bcode = 0u, bnode = kNone;
-    fallback_keys(list, L, weight, cl, seed, it, ant, step, lane, bcode, bnode);
+    fallback_keys(list, L, factor, cl, seed, it, ant, step, lane, bcode, bnode);
     return wave_select<4>(bcode, bnode);
 }
 
@@ -221,9 +241,9 @@ __host__ __device__ inline int list_cap(const Shape& s) {
 // fit in `cap` list entries (a wave prefix sum of their counts gives every
 // lane its first slot), lists those cities and keys them; the best key over
 // all passes wins (largest key, lowest city), as over one list of them all.
-template <class W>
+template <class F>
 __device__ __forceinline__ uint32_t fallback_bitmask(const BitmaskTabu& tabu, int n, uint16_t* list, int cap,
-                                                     const W& weight, int cl, uint64_t seed, uint32_t it, uint32_t ant,
+                                                     const F& factor, int cl, uint64_t seed, uint32_t it, uint32_t ant,
                                                      uint32_t step, int lane) {
     const int words = (n + 31) >> 5;
     uint32_t bcode = 0u, bnode = kNone;
@@ -249,7 +269,7 @@ __device__ __forceinline__ uint32_t fallback_bitmask(const BitmaskTabu& tabu, in
                 list[p++] = (uint16_t)(wi * 32 + b);
             }
         }
-        fallback_keys(list, L, weight, cl, seed, it, ant, step, lane, bcode, bnode);
+        fallback_keys(list, L, factor, cl, seed, it, ant, step, lane, bcode, bnode);
         w0 += nfit;
     }
     return wave_select<4>(bcode, bnode);
@@ -258,23 +278,105 @@ __device__ __forceinline__ uint32_t fallback_bitmask(const BitmaskTabu& tabu, in
 // The all-node fallback of the single-colony kernel, outlined (it is rare
 // with a list, and one copy serves every step of the unrolled step loop):
 // the same keys and winner as fallback_bitmask / fallback_list, but with the
-// LDS list and the global weight row passed with their address spaces (an
-// outlined function would otherwise reach both through flat accesses) and a
-// lane's four list entries keyed without branches. kList: the tabu lists the
-// unvisited cities itself (`list`, L entries); otherwise the bitmask `bits`
-// (n cities) is listed into `list` first. Weights: wrow[v] (dense trails) or
-// tmin_a * eta(drow[v])^beta (candidate-only trails).
-template <bool kList, int kPher>
-__device__ __attribute__((noinline)) uint32_t fallback_lone(LdsPtr<const uint32_t> bits, LdsPtr<uint16_t> list, int L,
-                                                            int n, GlbPtr<const float> wrow,
-                                                            GlbPtr<const int32_t> drow, float tmin_a, int beta,
-                                                            int cl, uint64_t seed, uint32_t it, uint32_t ant,
-                                                            uint32_t step, int lane) {
+// LDS tabu and the global factor row passed with their address spaces (an
+// outlined function would otherwise reach both through flat accesses) and
+// without branches around a lane's keys. Two layouts:
+//  - by list entries: a lane keys four entries of the list of the L
+//    unvisited cities a round (the compact and list tabus keep that list,
+//    the bitmask tabu's unvisited cities are listed into `list` first), one
+//    Philox block per entry;
+//  - by draw blocks: a lane takes the block of slots 4b .. 4b+3 a round,
+//    computes it once and keys each of its cities that is unvisited (every
+//    city is looked at, but a block serves four).
+// The cheaper one by instruction count is taken: a round of blocks costs a
+// Philox block (about 45) and four keys (about 45 each with the tabu test);
+// the list costs a Philox block and a key (about 85) for every 64 entries
+// (rounds whose entries are all past L are skipped), plus about 140 to list
+// a bitmask. `tabu`: the bitmask words,
+// the compact tabu's entries or the list tabu's unv (idx follows at n);
+// L: the number of unvisited cities. Key factors: irow[v], the reciprocal of
+// the weight (dense trails), or 1 / (tmin_a * eta(drow[v])^beta)
+// (candidate-only trails).
+// Wave-uniform values that arrive in vector registers (the arguments of an
+// outlined function) read back into scalar registers, so that the branches
+// and loops over them are scalar.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ float uni(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
+__device__ __forceinline__ uint64_t uni(uint64_t x) {
+    return ((uint64_t)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
+}
+template <class T>
+__device__ __forceinline__ T* uni_ptr(T* p) {
+    return reinterpret_cast<T*>(uni((uint64_t)reinterpret_cast<uintptr_t>(p)));
+}
+
+template <int kTabu, int kPher>
+__device__ __attribute__((noinline)) uint32_t fallback_lone(LdsPtr<const uint16_t> tabu_v, LdsPtr<uint16_t> list_v,
+                                                            int L_v, int n_v, GlbPtr<const float> irow_v,
+                                                            GlbPtr<const int32_t> drow_v, float tmin_a_v, int beta_v,
+                                                            int cl_v, uint64_t seed_v, uint32_t it_v, uint32_t ant_v,
+                                                            uint32_t step_v, int lane) {
+    constexpr bool kList = kTabu != MMAS_TABU_BITMASK;
+    const LdsPtr<const uint16_t> tabu = (LdsPtr<const uint16_t>)uni((uint32_t)(uintptr_t)tabu_v);
+    const LdsPtr<uint16_t> list = (LdsPtr<uint16_t>)uni((uint32_t)(uintptr_t)list_v);
+    const GlbPtr<const float> irow = (GlbPtr<const float>)uni((uint64_t)(uintptr_t)irow_v);
+    const GlbPtr<const int32_t> drow = (GlbPtr<const int32_t>)uni((uint64_t)(uintptr_t)drow_v);
+    int L = uni(L_v);
+    const int n = uni(n_v), beta = uni(beta_v), cl = uni(cl_v);
+    const float tmin_a = uni(tmin_a_v);
+    const uint64_t seed = uni(seed_v);
+    const uint32_t it = uni(it_v), ant = uni(ant_v), step = uni(step_v);
+    auto factor = [&](uint32_t v) -> float {
+        if constexpr (kPher == MMAS_PHER_DENSE)
+            return irow[v];
+        else
+            return 1.0f / (tmin_a * heur_from_dist(drow[v], beta));
+    };
+    const int b_lo = cl >> 2, nb = ((cl + n - 1) >> 2) - b_lo + 1;  // blocks holding slots cl .. cl + n - 1
+    const int rounds_b = (nb + kWave - 1) / kWave, per_lane = (L + kWave - 1) / kWave;
+    uint32_t bcode = 0u, bnode = kNone;
+    if (225 * rounds_b < 85 * per_lane + (kList ? 0 : 140)) {
+        for (int b0 = b_lo; b0 < b_lo + nb; b0 += kWave) {
+            const int b = b0 + lane;
+            uint32_t v[4];
+            bool ok[4];
+            float f[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = 4 * b + j - cl;
+                ok[j] = b < b_lo + nb && c >= 0 && c < n;
+                v[j] = ok[j] ? (uint32_t)c : 0u;
+            }
+            // the tabu and factor loads go out before the draws
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                bool seen;
+                if constexpr (kTabu == MMAS_TABU_BITMASK) {
+                    const LdsPtr<const uint32_t> bits = (LdsPtr<const uint32_t>)tabu;
+                    seen = (bits[v[j] >> 5] >> (v[j] & 31u)) & 1u;
+                } else if constexpr (kTabu == MMAS_TABU_COMPACT) {
+                    seen = tabu[v[j]] > v[j];
+                } else {
+                    seen = (int)tabu[n + v[j]] >= L;
+                }
+                ok[j] = ok[j] & !seen;
+                f[j] = factor(v[j]);
+            }
+            const Words4 blk = draw_block(seed, it, ant, step, (uint32_t)(4 * b));
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float key = log_u01(u01(blk.w[j])) * f[j];
+                keep_best(ok[j] ? ord_key(key) : 0u, v[j], bcode, bnode);
+            }
+        }
+        return wave_select<4>(bcode, bnode);
+    }
     if constexpr (!kList) {
         // every unvisited city in ascending order (one pass: room for n),
         // lane l taking 16-bit halves l, l + 64, ... of the bitmask, so that
         // a lane writes at most 16 entries
-        const LdsPtr<const uint16_t> halves = (LdsPtr<const uint16_t>)bits;
+        const LdsPtr<const uint16_t> halves = tabu;
         const int nh = (n + 15) >> 4;
         L = 0;
         for (int h0 = 0; h0 < nh; h0 += kWave) {
@@ -295,10 +397,9 @@ __device__ __attribute__((noinline)) uint32_t fallback_lone(LdsPtr<const uint32_
             L += __builtin_amdgcn_readlane(incl, 63);
         }
     }
-    uint32_t bcode = 0u, bnode = kNone;
     for (int base = 0; base < L; base += 4 * kWave) {
         uint32_t v[4];
-        float w[4];
+        float f[4];
         bool ok[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -306,19 +407,14 @@ __device__ __attribute__((noinline)) uint32_t fallback_lone(LdsPtr<const uint32_
             ok[u] = i < L;
             v[u] = list[ok[u] ? i : 0];
         }
-        // the weight loads go out before the draws and their logarithms
+        // the factor loads go out before the draws and their logarithms
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if constexpr (kPher == MMAS_PHER_DENSE)
-                w[u] = wrow[v[u]];
-            else
-                w[u] = tmin_a * heur_from_dist(drow[v[u]], beta);
-        }
+        for (int u = 0; u < 4; ++u) f[u] = factor(v[u]);
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const uint32_t slot = (uint32_t)cl + v[u];
             const Words4 blk = draw_block(seed, it, ant, step, slot);
-            const float key = log_u01(u01(pick_word(blk, slot & 3u))) * (1.0f / w[u]);
+            const float key = log_u01(u01(pick_word(blk, slot & 3u))) * f[u];
             const uint32_t code = ok[u] ? ord_key(key) : 0u;
             keep_best(code, v[u], bcode, bnode);
         }
@@ -330,12 +426,16 @@ __device__ __attribute__((noinline)) uint32_t fallback_lone(LdsPtr<const uint32_
 
 // What the leading wave (the one taking the steps) hands to the helper waves
 // of its workgroup for a fallback, and their per-wave results.
-struct WideLds {
-    int need[2];         // step k needs the fallback: need[k & 1] (the leading
-                         // wave writes step k+1's flag while a helper may still
-                         // read step k's)
+struct __align__(16) WideStep {
+    int need;            // the step needs the fallback
     uint32_t cur;        // current city
-    int L;               // compact tabu: unvisited count
+    int L;               // compact and list tabus: unvisited count
+    int stop;            // the leading wave found no city: every wave leaves
+};
+struct WideLds {
+    WideStep step[2];    // step k's record at step[k & 1] (the leading wave
+                         // writes step k+1's while a helper may still read
+                         // step k's)
     uint32_t counter;    // bitmask tabu: list fill counter
     unsigned long long res[16];  // per wave: (key code << 32) | ~city, 0 = none
 };
@@ -375,27 +475,27 @@ __device__ __forceinline__ unsigned long long share_result(uint32_t bcode, uint3
 // This wave's share of a workgroup-wide fallback (entries wave*64 + lane,
 // then every 64*waves): its best (key code, lowest city), packed so that the
 // larger value is the better one; 0 if the wave saw no city.
-template <class W>
-__device__ __forceinline__ unsigned long long fallback_share(const uint16_t* list, int L, const W& weight, int cl, uint64_t seed,
+template <class F>
+__device__ __forceinline__ unsigned long long fallback_share(const uint16_t* list, int L, const F& factor, int cl, uint64_t seed,
                                              uint32_t it, uint32_t ant, uint32_t step, int lane, int wv, int nw) {
     uint32_t bcode = 0u, bnode = kNone;
     const int stride = kWave * nw;
     for (int base = wv * kWave; base < L; base += 4 * stride) {
         uint32_t v[4];
-        float w[4];
+        float f[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int i = base + u * stride + lane;
             v[u] = i < L ? (uint32_t)list[i] : kNone;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) w[u] = v[u] != kNone ? weight(v[u]) : 1.0f;
+        for (int u = 0; u < 4; ++u) f[u] = v[u] != kNone ? factor(v[u]) : 1.0f;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             if (v[u] == kNone) continue;
             const uint32_t slot = (uint32_t)cl + v[u];
             const Words4 blk = draw_block(seed, it, ant, step, slot);
-            const float key = log_u01(u01(pick_word(blk, slot & 3u))) * (1.0f / w[u]);
+            const float key = log_u01(u01(pick_word(blk, slot & 3u))) * f[u];
             keep_best(ord_key(key), v[u], bcode, bnode);
         }
     }
@@ -408,8 +508,8 @@ __device__ __forceinline__ unsigned long long fallback_share(const uint16_t* lis
 // and keys each of its cities (slot - cl) that is unvisited. While most
 // cities are unvisited this needs a quarter of the blocks of the list layout;
 // the keys, and so the winner, are the same.
-template <class T, class W>
-__device__ __forceinline__ unsigned long long fallback_share_blocks(const T& tabu, int n, const W& weight, int cl,
+template <class T, class F>
+__device__ __forceinline__ unsigned long long fallback_share_blocks(const T& tabu, int n, const F& factor, int cl,
                                                                     uint64_t seed, uint32_t it, uint32_t ant,
                                                                     uint32_t step, int lane, int wv, int nw) {
     uint32_t bcode = 0u, bnode = kNone;
@@ -422,7 +522,7 @@ __device__ __forceinline__ unsigned long long fallback_share_blocks(const T& tab
             for (int j = 0; j < 4; ++j) {
                 const int v = 4 * b + j - cl;
                 if (v < 0 || v >= n || tabu.visited((uint32_t)v)) continue;
-                const float key = log_u01(u01(blk.w[j])) * (1.0f / weight((uint32_t)v));
+                const float key = log_u01(u01(blk.w[j])) * factor((uint32_t)v);
                 keep_best(ord_key(key), (uint32_t)v, bcode, bnode);
             }
         }
@@ -461,9 +561,11 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
                               const uint16_t* tcand, const float* tchc, int R, WideLds* wl = nullptr) {
     const int n = s.n, cl = s.cl;
     const uint64_t seed = s.seed;
-    const int wv = kWide ? (int)(threadIdx.x >> 6) : 0;
+    // (wave-uniform: scalar branches between the leading wave and the helpers)
+    const int wv = kWide ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
     const int nw = kWide ? (int)(blockDim.x >> 6) : 1;
     const bool lead = wv == 0;
+    bool stop = false;  // kWide: the leading wave found no city at the last step
 
     // per-ant LDS: the draws of the next steps (256 floats), then the tabu
     float* lnbuf = reinterpret_cast<float*>(region);
@@ -548,30 +650,36 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
             next = wave_select_step<4>(code, node);
         }
         if constexpr (kWide) {
-            // the helpers learn whether this step needs them
+            // the helpers learn whether this step needs them (one record)
             if (lead && lane == 0) {
-                wl->need[k & 1] = next == kNone ? 1 : 0;
-                wl->cur = cur;
+                WideStep st;
+                st.need = next == kNone ? 1 : 0;
+                st.cur = cur;
+                st.L = 0;
+                if constexpr (kTabu != MMAS_TABU_BITMASK) st.L = tabu.L;
+                st.stop = stop ? 1 : 0;
+                wl->step[k & 1] = st;
                 if constexpr (kTabu == MMAS_TABU_BITMASK) wl->counter = 0u;
-                else wl->L = tabu.L;
             }
             __syncthreads();
-            const bool need = wl->need[k & 1] != 0;
+            const WideStep st = wl->step[k & 1];
+            if (__builtin_amdgcn_readfirstlane(st.stop)) break;
+            const bool need = __builtin_amdgcn_readfirstlane(st.need) != 0;
             if (__builtin_expect(need, 0)) {
                 if (lead) {
                     fb_steps += 1;
                     fb_nodes += n - k;
                 }
-                const uint32_t fcur = wl->cur;
+                const uint32_t fcur = (uint32_t)__builtin_amdgcn_readfirstlane((int)st.cur);
                 const uint16_t* list;
                 int L;
                 if constexpr (kTabu == MMAS_TABU_BITMASK) {
                     gather_unvisited_block(tabu, n, ulist, &wl->counter);
                     __syncthreads();
-                    L = (int)wl->counter;
+                    L = __builtin_amdgcn_readfirstlane((int)wl->counter);
                     list = ulist;
                 } else {
-                    L = wl->L;
+                    L = __builtin_amdgcn_readfirstlane(st.L);
                     list = tabu.list();
                     if constexpr (kTabu == MMAS_TABU_LIST) tabu.L = L;  // the helpers' copy of the length
                 }
@@ -580,30 +688,43 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
                 const bool by_blocks = kTabu != MMAS_TABU_BITMASK && 46 * L > 25 * n;
                 unsigned long long mine;
                 if constexpr (kPher == MMAS_PHER_DENSE) {
-                    const DenseWeight wt{vw.choice + (size_t)fcur * n};
+                    const DenseFactor wt{vw.choice_inv + (size_t)fcur * n};
                     mine = by_blocks
                                ? fallback_share_blocks(tabu, n, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw)
                                : fallback_share(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw);
                 } else {
-                    const CandWeight wt{dist + (size_t)fcur * n, tmin_a, s.beta};
+                    const CandFactor wt{dist + (size_t)fcur * n, tmin_a, s.beta};
                     mine = by_blocks
                                ? fallback_share_blocks(tabu, n, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw)
                                : fallback_share(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw);
                 }
                 if (lane == 0) wl->res[wv] = mine;
                 __syncthreads();
-                unsigned long long best = lane < nw ? wl->res[lane] : 0ull;
-                for (int o = 32; o >= 1; o >>= 1) {
-                    const unsigned long long other = __shfl_xor(best, o);
-                    best = other > best ? other : best;
+                if (lead) {
+                    // the best over the waves (lanes 0 .. nw-1, one row): the
+                    // largest key code, then the largest ~city
+                    const unsigned long long r = lane < nw ? wl->res[lane] : 0ull;
+                    const uint32_t hi = (uint32_t)(r >> 32), lo = (uint32_t)r;
+                    const uint32_t mx = wave_max_u32<2>(hi);
+                    uint32_t best_lo;
+                    const uint64_t tied = __ballot(hi == mx && lane < nw);
+                    if (__popcll(tied) == 1)
+                        best_lo = (uint32_t)__builtin_amdgcn_readlane((int)lo, __ffsll((unsigned long long)tied) - 1);
+                    else
+                        best_lo = wave_max_u32<2>(hi == mx ? lo : 0u);
+                    next = mx ? ~best_lo : kNone;
                 }
-                next = (best >> 32) ? ~(uint32_t)best : kNone;
-                // (cur, L, the counter and the list of this step are read before
-                // the last barrier; res is written again only after the next
-                // step's first barrier)
+                // (the record, the counter and the list of this step are read
+                // before the last barrier; res is written again only after the
+                // next step's first barrier)
             }
-            if (!lead) {
-                if (need && next >= (uint32_t)n) break;  // the leading wave breaks too
+            if (!lead) continue;
+            if (next >= (uint32_t)n) {
+                // unreachable with a validated instance: report it, and let
+                // every wave leave at the next step's record
+                if (lane == 0) atomicOr(&vw.state->flags, 8u);
+                stop = true;
+                if (k == n - 1) break;
                 continue;
             }
         } else if (next == kNone) {
@@ -611,13 +732,13 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
             fb_nodes += n - k;
             const int cap = list_cap(s);
             if constexpr (kPher == MMAS_PHER_DENSE) {
-                const DenseWeight wt{vw.choice + (size_t)cur * n};
+                const DenseFactor wt{vw.choice_inv + (size_t)cur * n};
                 if constexpr (kTabu == MMAS_TABU_BITMASK)
                     next = fallback_bitmask(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
                 else
                     next = fallback_list(tabu.list(), tabu.L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
             } else {
-                const CandWeight wt{dist + (size_t)cur * n, tmin_a, s.beta};
+                const CandFactor wt{dist + (size_t)cur * n, tmin_a, s.beta};
                 if constexpr (kTabu == MMAS_TABU_BITMASK)
                     next = fallback_bitmask(tabu, n, ulist, cap, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
                 else
@@ -728,17 +849,19 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
         fb_steps += 1;
         fb_nodes += n - kk;
         // (C-style casts: the only casts that change the address space)
-        const GlbPtr<const float> wrow =
-            kPher == MMAS_PHER_DENSE ? (GlbPtr<const float>)(vw.choice + (size_t)cur * n) : nullptr;
+        const GlbPtr<const float> irow =
+            kPher == MMAS_PHER_DENSE ? (GlbPtr<const float>)(vw.choice_inv + (size_t)cur * n) : nullptr;
         const GlbPtr<const int32_t> drow =
             kPher == MMAS_PHER_DENSE ? nullptr : (GlbPtr<const int32_t>)(dist + (size_t)cur * n);
         uint32_t pick;
         if constexpr (kTabu == MMAS_TABU_BITMASK)
-            pick = fallback_lone<false, kPher>((LdsPtr<const uint32_t>)tabu.bits, (LdsPtr<uint16_t>)ulist, 0, n, wrow,
-                                               drow, tmin_a, s.beta, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+            pick = fallback_lone<kTabu, kPher>((LdsPtr<const uint16_t>)tabu.bits, (LdsPtr<uint16_t>)ulist, n - kk, n,
+                                               irow, drow, tmin_a, s.beta, cl, seed, it, (uint32_t)ant, (uint32_t)k,
+                                               lane);
         else
-            pick = fallback_lone<true, kPher>(nullptr, (LdsPtr<uint16_t>)tabu.list(), tabu.L, n, wrow, drow, tmin_a,
-                                              s.beta, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+            pick = fallback_lone<kTabu, kPher>((LdsPtr<const uint16_t>)tabu.list(), (LdsPtr<uint16_t>)tabu.list(), tabu.L,
+                                               n, irow, drow, tmin_a, s.beta, cl, seed, it, (uint32_t)ant, (uint32_t)k,
+                                               lane);
         const uint32_t next = (uint32_t)__builtin_amdgcn_readfirstlane((int)pick);
         // no city is unreachable with a validated instance; were it not,
         // report it after the tour and go on with city 0 (the tour is void)
@@ -945,7 +1068,7 @@ __device__ uint32_t fallback_step(const Views& vw, const Shape& s, uint32_t it, 
                                   const Tabu& tabu, uint8_t* region, float tmin_a, int lane) {
     const int n = s.n;
     if constexpr (kPher == MMAS_PHER_DENSE) {
-        const DenseWeight wt{vw.choice + (size_t)cur * n};
+        const DenseFactor wt{vw.choice_inv + (size_t)cur * n};
         if constexpr (kTabu == MMAS_TABU_BITMASK) {
             uint16_t* ulist = reinterpret_cast<uint16_t*>(region + kDrawBytes + kScratchBytes + align16(4 * ((n + 31) / 32)));
             return fallback_bitmask(tabu, n, ulist, list_cap(s), wt, s.cl, s.seed, it, ant, (uint32_t)k, lane);
@@ -953,7 +1076,7 @@ __device__ uint32_t fallback_step(const Views& vw, const Shape& s, uint32_t it, 
             return fallback_list(tabu.list(), tabu.L, wt, s.cl, s.seed, it, ant, (uint32_t)k, lane);
         }
     } else {
-        const CandWeight wt{vw.dist + (size_t)cur * n, tmin_a, s.beta};
+        const CandFactor wt{vw.dist + (size_t)cur * n, tmin_a, s.beta};
         if constexpr (kTabu == MMAS_TABU_BITMASK) {
             uint16_t* ulist = reinterpret_cast<uint16_t*>(region + kDrawBytes + kScratchBytes + align16(4 * ((n + 31) / 32)));
             return fallback_bitmask(tabu, n, ulist, list_cap(s), wt, s.cl, s.seed, it, ant, (uint32_t)k, lane);
@@ -1022,7 +1145,7 @@ __device__ void construct_pair(const Views& vw, const Shape& s, uint32_t it, int
     const int G = 1 << gsh;
     const int S = 32 >> gsh;
     const int lr = hl < cl ? hl : cl - 1;
-    const uint32_t lane_ok = (hl < cl) & (h == 0 || hasB) ? ~0u : 0u;
+    const uint32_t lane_ok = ((hl < cl) & (h == 0 || hasB)) ? ~0u : 0u;
     const int ln_lane = hl & (4 * G - 1);
 
     uint16_t* tour_out = vw.tours + (size_t)my_ant * n;
@@ -1175,6 +1298,116 @@ __global__ __launch_bounds__(1024) void k_construct_wide(Views vw, Shape s, uint
     if (R > 0) stage_table(vw, s.cl, R, tcand, tchc);
     __syncthreads();
     construct_ant<kTabu, kPher, true>(vw, s, it, (int)blockIdx.x, lane, smem + lds.table_bytes, tcand, tchc, R, &wl);
+}
+
+// Without candidate lists, for small instances with SIMDs to spare: a team
+// of four waves per ant and no shared tabu. Every step keys all unvisited
+// cities (Alg. 4 over all of them, as the fallback does); the cities are
+// split by their word in the draw block: wave j takes city 4b + j of every
+// block b, so the four waves compute the same Philox blocks (one per lane and
+// round) and each keys one word of them. A wave keeps the visited bits of its
+// cities in a register (bit r of lane l: city 4 (64 r + l) + j; the bitmask
+// tabu held in registers). One barrier a step: each wave posts its best
+// (key code, city), and all four read the four and take the same winner, so
+// each knows the next city without a second exchange. n <= 1024 (at most four
+// rounds of 64 blocks).
+template <int kPher>
+__global__ __launch_bounds__(256) void k_construct_team(Views vw, Shape s, uint32_t it) {
+    __shared__ unsigned long long res[2][4];  // by step parity: each wave's best
+    const int lane = threadIdx.x & 63;
+    const int j = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));  // word of the block
+    const int ant = blockIdx.x;
+    const int n = s.n;
+    const uint64_t seed = s.seed;
+    const int rounds = (((n + 3) >> 2) + kWave - 1) / kWave;  // <= 4
+    float tmin_a = 0.0f;
+    if (kPher == MMAS_PHER_CANDIDATES) tmin_a = powi(vw.state->tau_min, s.alpha);
+    const uint32_t x0 = draw_block(seed, it, (uint32_t)ant, 0u, 0u).w[0];
+    const int start = __builtin_amdgcn_readfirstlane((int)(((uint64_t)x0 * (uint64_t)n) >> 32));
+    // visited bits; cities past n count as visited
+    uint32_t vis = 0u;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (r >= rounds || 4 * (kWave * r + lane) + j >= n) vis |= 1u << r;
+    auto mark = [&](int c) {
+        if ((c & 3) == j && lane == ((c >> 2) & (kWave - 1))) vis |= 1u << (c >> 8);
+    };
+    mark(start);
+
+    uint16_t* tour_out = vw.tours + (size_t)ant * n;
+    const int32_t* dist = vw.dist;
+    uint32_t tbuf = (uint32_t)start;  // first wave: lane (k & 63) holds the city of step k
+    uint32_t prev_last = 0;
+    int64_t len = 0;
+    int cur = start;
+    for (int k = 1; k < n; ++k) {
+        // the factors and visited bits first, then the draws
+        float f[4];
+        uint32_t v[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int c = 4 * (kWave * r + lane) + j;
+            v[r] = c < n ? (uint32_t)c : 0u;
+            if (kPher == MMAS_PHER_DENSE)
+                f[r] = r < rounds ? vw.choice_inv[(size_t)cur * n + v[r]] : 1.0f;
+            else
+                f[r] = r < rounds ? 1.0f / (tmin_a * heur_from_dist(dist[(size_t)cur * n + v[r]], s.beta)) : 1.0f;
+        }
+        uint32_t bcode = 0u, bnode = kNone;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            if (r >= rounds) break;
+            const Words4 blk = draw_block(seed, it, (uint32_t)ant, (uint32_t)k, (uint32_t)(4 * (kWave * r + lane)));
+            const float key = log_u01(u01(pick_word(blk, (uint32_t)j))) * f[r];
+            keep_best(((vis >> r) & 1u) ? 0u : ord_key(key), v[r], bcode, bnode);
+        }
+        const unsigned long long mine = share_result(bcode, bnode);
+        if (lane == 0) res[k & 1][j] = mine;
+        __syncthreads();
+        // every wave takes the same winner: the largest key code, then the
+        // largest ~city (res[k & 1] is written again two steps later, after
+        // the next barrier)
+        const unsigned long long rr = lane < 4 ? res[k & 1][lane] : 0ull;
+        const uint32_t hi = (uint32_t)(rr >> 32), lo = (uint32_t)rr;
+        const uint32_t mx = wave_max_u32<2>(hi);
+        const uint64_t tied = __ballot(hi == mx && lane < 4);
+        uint32_t best_lo;
+        if (__popcll(tied) == 1)
+            best_lo = (uint32_t)__builtin_amdgcn_readlane((int)lo, __ffsll((unsigned long long)tied) - 1);
+        else
+            best_lo = wave_max_u32<2>(hi == mx ? lo : 0u);
+        const uint32_t next = mx ? ~best_lo : kNone;
+        if (next >= (uint32_t)n) {
+            // unreachable with a validated instance; every wave leaves
+            if (j == 0 && lane == 0) atomicOr(&vw.state->flags, 8u);
+            break;
+        }
+        mark((int)next);
+        cur = (int)next;
+        if (j == 0) {
+            const int slot = k & 63;
+            if (lane == slot) tbuf = next;
+            if (slot == 63 || k == n - 1) {
+                // flush the chunk of steps k0 .. k; lane l holds step k0 + l
+                const int k0 = k - slot;
+                const uint32_t prev = __shfl_up(tbuf, 1);
+                if (lane <= slot) {
+                    tour_out[k0 + lane] = (uint16_t)tbuf;
+                    const uint32_t from = lane == 0 ? prev_last : prev;
+                    if (k0 + lane > 0) len += dist[(size_t)from * n + tbuf];
+                }
+                prev_last = (uint32_t)__builtin_amdgcn_readlane((int)tbuf, slot);
+            }
+        }
+    }
+    if (j != 0) return;
+    if (lane == 0) len += dist[(size_t)cur * n + start];  // closing edge
+    len = wave_sum_i64(len);
+    if (lane == 0) {
+        vw.lengths[ant] = len;
+        vw.fallback[ant] = n - 1;                                 // every step is a fallback
+        vw.fallback[s.ants + ant] = (int64_t)n * (n - 1) / 2;     // over n - k cities at step k
+    }
 }
 
 // Batched construction: a persistent grid pulls tiles (instance, first ant of
@@ -1353,8 +1586,25 @@ hipError_t launch_wide(const Views& v, const Shape& s, uint32_t it, int waves, h
     return hipGetLastError();
 }
 
+// The team kernel (four waves per ant, no list, bitmask tabu, n <= 1024):
+// asked for with four waves per ant, or by default while every ant's four
+// waves find SIMDs of their own.
+bool team_ok(const Shape& s) {
+    if (s.cl != 0 || s.tabu != MMAS_TABU_BITMASK || s.n > 1024 || s.select != MMAS_SELECT_WRS) return false;
+    if (s.construct_waves > 0) return s.construct_waves == 4;
+    const int simds = device_attr(g_simds, hipDeviceAttributeMultiprocessorCount, 4, 0);
+    return 4 * s.ants <= simds;
+}
+
+template <int kPher>
+hipError_t launch_team(const Views& v, const Shape& s, uint32_t it, hipStream_t st) {
+    k_construct_team<kPher><<<s.ants, 4 * kWave, 0, st>>>(v, s, it);
+    return hipGetLastError();
+}
+
 template <int kTabu, int kPher>
 hipError_t launch_tp(const Views& v, const Shape& s, uint32_t it, hipStream_t st) {
+    if (kTabu == MMAS_TABU_BITMASK && team_ok(s)) return launch_team<kPher>(v, s, it, st);
     if (pair_ok(s)) return launch_t<kTabu, kPher, true>(v, s, it, st);
     const int waves = construct_waves(s);
     if (waves > 1) return launch_wide<kTabu, kPher>(v, s, it, waves, st);
@@ -1526,7 +1776,7 @@ __global__ __launch_bounds__(256) void k_construct_prwm(Views vw, Shape s, uint3
             const int e = (int)cur * cl + (lane < cl ? lane : cl - 1);
             const uint32_t node = vw.cand[e];
             const float w = vw.chc[e];
-            const float a = (lane < cl) & !tabu.visited(node) ? w : 0.0f;
+            const float a = ((lane < cl) & !tabu.visited(node)) ? w : 0.0f;
             const uint64_t pos = __ballot(a > 0.0f);
             if (pos) {
                 const float P = wave_scan_f32(a, lane);

@@ -16,6 +16,7 @@ struct Views {
     float* heur;        // n*n (dense) or n*cl (candidates): eta^beta
     float* tau;         // n*n (dense) or n*cl (candidates)
     float* choice;      // n*n (dense) or nullptr
+    float* choice_inv;  // n*n (dense) or nullptr: 1 / choice (IEEE division), the fallback keys' factor
     float* chc;         // n*cl
     float* chc_inv;     // n*cl: 1 / chc (IEEE division), the key's factor
     uint16_t* cand;     // n*cl

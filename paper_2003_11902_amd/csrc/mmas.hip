@@ -26,7 +26,7 @@ struct mmas_ctx {
     size_t ws_bytes;
     size_t off[MMAS_BUF_COUNT];
     size_t len[MMAS_BUF_COUNT];
-    size_t off_succ, off_pred, off_nnd, off_inv;
+    size_t off_succ, off_pred, off_nnd, off_inv, off_cinv;
     bool choice_stale;
     bool constructed;
     // per-call timing (mmas_set_timing): event pairs not yet read, and the totals
@@ -88,7 +88,7 @@ Shape shape_of(const mmas_params* p) {
 
 // Byte sizes of every view, then their offsets (256-byte aligned).
 size_t layout(const Shape& s, size_t* off, size_t* len, size_t* off_succ, size_t* off_pred, size_t* off_nnd,
-              size_t* off_inv) {
+              size_t* off_inv, size_t* off_cinv) {
     const size_t n = (size_t)s.n, cl = (size_t)s.cl, ants = (size_t)s.ants;
     const bool dense = s.pher == MMAS_PHER_DENSE;
     len[MMAS_BUF_DIST] = 4 * n * n;
@@ -117,6 +117,8 @@ size_t layout(const Shape& s, size_t* off, size_t* len, size_t* off_succ, size_t
     pos = align_up(pos + 4 * n * (size_t)s.ls_nn);
     *off_inv = pos;  // 1 / chc along the candidate lists
     pos = align_up(pos + 4 * n * cl);
+    *off_cinv = pos;  // 1 / choice_info, dense trails
+    pos = align_up(pos + (dense ? 4 * n * n : 0));
     return pos;
 }
 
@@ -207,8 +209,8 @@ extern "C" {
 size_t mmas_workspace_bytes(const mmas_params* p) {
     if (!params_ok(p)) return 0;
     Shape s = shape_of(p);
-    size_t off[MMAS_BUF_COUNT], len[MMAS_BUF_COUNT], os, op, od, oi;
-    return layout(s, off, len, &os, &op, &od, &oi);
+    size_t off[MMAS_BUF_COUNT], len[MMAS_BUF_COUNT], os, op, od, oi, oc;
+    return layout(s, off, len, &os, &op, &od, &oi, &oc);
 }
 
 mmas_status mmas_create(const int32_t* dist_host, const mmas_params* p, void* dev_ws, size_t ws_bytes,
@@ -225,7 +227,7 @@ mmas_status mmas_create(const int32_t* dist_host, const mmas_params* p, void* de
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->ws = reinterpret_cast<char*>(dev_ws);
     c->ws_bytes = ws_bytes;
-    const size_t need = layout(s, c->off, c->len, &c->off_succ, &c->off_pred, &c->off_nnd, &c->off_inv);
+    const size_t need = layout(s, c->off, c->len, &c->off_succ, &c->off_pred, &c->off_nnd, &c->off_inv, &c->off_cinv);
     if (ws_bytes < need) {
         delete c;
         return MMAS_ENOSPACE;
@@ -260,6 +262,7 @@ mmas_status mmas_create(const int32_t* dist_host, const mmas_params* p, void* de
     v.state = at<mmas_device_state>(b, c->off[MMAS_BUF_STATE], c->len[MMAS_BUF_STATE]);
     v.lsnn = at<uint16_t>(b, c->off[MMAS_BUF_LSNN], c->len[MMAS_BUF_LSNN]);
     v.chc_inv = c->len[MMAS_BUF_CHC] ? reinterpret_cast<float*>(b + c->off_inv) : nullptr;
+    v.choice_inv = c->len[MMAS_BUF_CHOICE] ? reinterpret_cast<float*>(b + c->off_cinv) : nullptr;
     v.succ = reinterpret_cast<uint16_t*>(b + c->off_succ);
     v.pred = reinterpret_cast<uint16_t*>(b + c->off_pred);
 

@@ -1,7 +1,7 @@
 // Per-iteration kernels around construction (Alg. 1, Sec. 2.1):
 //  - choice_info = tau^alpha * eta^beta, dense and along the candidate lists,
-//    and along the lists also its reciprocal (Sec. 4.2.2: the reciprocal of
-//    every weight computed once per iteration, so that a key is a product);
+//    and its reciprocal beside both (Sec. 4.2.2: the reciprocal of every
+//    weight computed once per iteration, so that a key is a product);
 //  - the iteration best, the global best and the trail limits (one workgroup);
 //  - evaporation, deposit on both directions of the iteration best's edges (on
 //    (i, succ(i)) alone for the asymmetric TSP) and the [tau_min, tau_max] clamp, fused with the refresh of choice_info (the
@@ -16,13 +16,18 @@ namespace {
 // dense: one workgroup per row
 __global__ __launch_bounds__(256) void k_choice_dense(const float* __restrict__ tau, const float* __restrict__ heur,
                                                       const uint16_t* __restrict__ cand, int n, int cl, int alpha,
-                                                      float* __restrict__ choice, float* __restrict__ chc,
-                                                      float* __restrict__ chc_inv) {
+                                                      float* __restrict__ choice, float* __restrict__ choice_inv,
+                                                      float* __restrict__ chc, float* __restrict__ chc_inv) {
     const size_t i = blockIdx.x;
     const float* trow = tau + i * n;
     const float* hrow = heur + i * n;
     float* crow = choice + i * n;
-    for (int j = threadIdx.x; j < n; j += blockDim.x) crow[j] = powi(trow[j], alpha) * hrow[j];
+    float* irow = choice_inv + i * n;
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const float c = powi(trow[j], alpha) * hrow[j];
+        crow[j] = c;
+        irow[j] = 1.0f / c;
+    }
     for (int r = threadIdx.x; r < cl; r += blockDim.x) {
         const int j = cand[i * cl + r];
         const float c = powi(trow[j], alpha) * hrow[j];
@@ -143,6 +148,7 @@ __device__ void update_dense_row(const Views& vw, const Shape& s, size_t i) {
     float* trow = vw.tau + i * n;
     const float* hrow = vw.heur + i * n;
     float* crow = vw.choice + i * n;
+    float* irow = vw.choice_inv + i * n;
     for (int r = threadIdx.x; r < cl; r += blockDim.x) {
         const int j = vw.cand[i * cl + r];
         const float t = evaporate_deposit(trow[j], j == si || j == pi, keep, tmin, tmax, delta);
@@ -154,7 +160,9 @@ __device__ void update_dense_row(const Views& vw, const Shape& s, size_t i) {
     for (int j = threadIdx.x; j < n; j += blockDim.x) {
         const float t = evaporate_deposit(trow[j], j == si || j == pi, keep, tmin, tmax, delta);
         trow[j] = t;
-        crow[j] = powi(t, s.alpha) * hrow[j];
+        const float c = powi(t, s.alpha) * hrow[j];
+        crow[j] = c;
+        irow[j] = 1.0f / c;
     }
 }
 
@@ -233,7 +241,8 @@ int grid_for(size_t total, int block) {
 
 hipError_t launch_choice(const Views& v, const Shape& s, hipStream_t st) {
     if (s.pher == MMAS_PHER_DENSE) {
-        k_choice_dense<<<s.n, 256, 0, st>>>(v.tau, v.heur, v.cand, s.n, s.cl, s.alpha, v.choice, v.chc, v.chc_inv);
+        k_choice_dense<<<s.n, 256, 0, st>>>(v.tau, v.heur, v.cand, s.n, s.cl, s.alpha, v.choice, v.choice_inv, v.chc,
+                                            v.chc_inv);
     } else {
         const size_t count = (size_t)s.n * s.cl;
         k_choice_cand<<<grid_for(count, 256), 256, 0, st>>>(v.tau, v.heur, count, s.alpha, v.chc, v.chc_inv);

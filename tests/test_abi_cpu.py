@@ -41,8 +41,8 @@ def test_workspace_bytes(M):
     p = M.make_params(1002, 1002, 32)
     b = M.mmas_workspace_bytes(p)
     n = 1002
-    # dist, heur, tau, choice: four n*n arrays dominate
-    assert 18 * n * n < b < 18 * n * n + (1 << 20)  # + tours (2 n ants)
+    # dist, heur, tau, choice and its reciprocal: five n*n arrays dominate
+    assert 22 * n * n < b < 22 * n * n + (1 << 20)  # + tours (2 n ants)
     assert M.mmas_workspace_bytes(M.make_params(1002, 1002, 32, problem="atsp")) == b
     pc = M.make_params(18512, 64, 16, pher="candidates", ls_nn=8)
     bc = M.mmas_workspace_bytes(pc)
