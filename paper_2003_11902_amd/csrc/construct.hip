@@ -427,15 +427,14 @@ __device__ __attribute__((noinline)) uint32_t fallback_lone(LdsPtr<const uint16_
 // What the leading wave (the one taking the steps) hands to the helper waves
 // of its workgroup for a fallback, and their per-wave results.
 struct __align__(16) WideStep {
-    int need;            // the step needs the fallback
+    int k;               // the step that needs the fallback
     uint32_t cur;        // current city
     int L;               // compact and list tabus: unvisited count
-    int stop;            // the leading wave found no city: every wave leaves
+    int stop;            // the tour is done: every wave leaves
 };
 struct WideLds {
-    WideStep step[2];    // step k's record at step[k & 1] (the leading wave
-                         // writes step k+1's while a helper may still read
-                         // step k's)
+    WideStep step;       // written by the leading wave before the first barrier
+                         // of a fallback, read by all after it
     uint32_t counter;    // bitmask tabu: list fill counter
     unsigned long long res[16];  // per wave: (key code << 32) | ~city, 0 = none
 };
@@ -551,6 +550,38 @@ __device__ void stage_table(const Views& vw, int cl, int R, uint16_t* tcand, flo
     }
 }
 
+// One wave's share of a workgroup-wide fallback at step k from city fcur
+// (the bitmask tabu's unvisited cities are first gathered by the whole
+// workgroup, with a barrier): the wave's best (key code, ~city), 0 if none.
+template <int kTabu, int kPher, class T>
+__device__ unsigned long long wide_share(const Views& vw, const Shape& s, uint32_t it, int ant, int k, uint32_t fcur,
+                                         int L, T& tabu, uint16_t* ulist, WideLds* wl, float tmin_a, int lane, int wv,
+                                         int nw) {
+    const int n = s.n, cl = s.cl;
+    const uint16_t* list;
+    if constexpr (kTabu == MMAS_TABU_BITMASK) {
+        gather_unvisited_block(tabu, n, ulist, &wl->counter);
+        __syncthreads();
+        L = __builtin_amdgcn_readfirstlane((int)wl->counter);
+        list = ulist;
+    } else {
+        list = tabu.list();
+        if constexpr (kTabu == MMAS_TABU_LIST) tabu.L = L;  // the helpers' copy of the length
+    }
+    // by draw blocks while they are cheaper: a block costs about a Philox
+    // and four keys, a listed city a Philox and one key
+    const bool by_blocks = kTabu != MMAS_TABU_BITMASK && 46 * L > 25 * n;
+    if constexpr (kPher == MMAS_PHER_DENSE) {
+        const DenseFactor wt{vw.choice_inv + (size_t)fcur * n};
+        return by_blocks ? fallback_share_blocks(tabu, n, wt, cl, s.seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw)
+                         : fallback_share(list, L, wt, cl, s.seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw);
+    } else {
+        const CandFactor wt{vw.dist + (size_t)fcur * n, tmin_a, s.beta};
+        return by_blocks ? fallback_share_blocks(tabu, n, wt, cl, s.seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw)
+                         : fallback_share(list, L, wt, cl, s.seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw);
+    }
+}
+
 // One ant's tour (one wave64): start city, n - 1 selection steps, tour and
 // length stores. `region` is the ant's LDS region; rows 0..R-1 of the
 // candidate table are in LDS at tcand / tchc.
@@ -565,7 +596,6 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
     const int wv = kWide ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
     const int nw = kWide ? (int)(blockDim.x >> 6) : 1;
     const bool lead = wv == 0;
-    bool stop = false;  // kWide: the leading wave found no city at the last step
 
     // per-ant LDS: the draws of the next steps (256 floats), then the tabu
     float* lnbuf = reinterpret_cast<float*>(region);
@@ -605,9 +635,29 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
     int64_t fb_steps = 0, fb_nodes = 0;
     uint32_t cur = start;
 
+    if constexpr (kWide) {
+        if (!lead) {
+            // Helper waves serve the fallbacks only: they wait at the barrier
+            // until the leading wave posts one (or the end of its tour), so
+            // that the steps without a fallback need no barrier.
+            for (;;) {
+                __syncthreads();  // a posted fallback, or the end
+                const WideStep st = wl->step;
+                if (__builtin_amdgcn_readfirstlane(st.stop)) return;
+                const unsigned long long mine =
+                    wide_share<kTabu, kPher>(vw, s, it, ant, __builtin_amdgcn_readfirstlane(st.k),
+                                             (uint32_t)__builtin_amdgcn_readfirstlane((int)st.cur),
+                                             __builtin_amdgcn_readfirstlane(st.L), tabu, ulist, wl, tmin_a, lane, wv,
+                                             nw);
+                if (lane == 0) wl->res[wv] = mine;
+                __syncthreads();  // the results (read by the leading wave)
+            }
+        }
+    }
+
     for (int k = 1; k < n; ++k) {
         uint32_t next = kNone;
-        if (lead && cl > 0) {
+        if (cl > 0) {
             // candidate phase: lane r holds rank r of cur's list
             // every lane loads a valid entry (lanes past the list repeat the
             // last one and get no key); the row comes from LDS or from global
@@ -650,82 +700,42 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
             next = wave_select_step<4>(code, node);
         }
         if constexpr (kWide) {
-            // the helpers learn whether this step needs them (one record)
-            if (lead && lane == 0) {
-                WideStep st;
-                st.need = next == kNone ? 1 : 0;
-                st.cur = cur;
-                st.L = 0;
-                if constexpr (kTabu != MMAS_TABU_BITMASK) st.L = tabu.L;
-                st.stop = stop ? 1 : 0;
-                wl->step[k & 1] = st;
-                if constexpr (kTabu == MMAS_TABU_BITMASK) wl->counter = 0u;
-            }
-            __syncthreads();
-            const WideStep st = wl->step[k & 1];
-            if (__builtin_amdgcn_readfirstlane(st.stop)) break;
-            const bool need = __builtin_amdgcn_readfirstlane(st.need) != 0;
-            if (__builtin_expect(need, 0)) {
-                if (lead) {
-                    fb_steps += 1;
-                    fb_nodes += n - k;
+            if (__builtin_expect(next == kNone, 0)) {
+                // post the fallback; every wave keys its share of it
+                fb_steps += 1;
+                fb_nodes += n - k;
+                if (lane == 0) {
+                    WideStep st;
+                    st.k = k;
+                    st.cur = cur;
+                    st.L = 0;
+                    if constexpr (kTabu != MMAS_TABU_BITMASK) st.L = tabu.L;
+                    st.stop = 0;
+                    wl->step = st;
+                    if constexpr (kTabu == MMAS_TABU_BITMASK) wl->counter = 0u;
                 }
-                const uint32_t fcur = (uint32_t)__builtin_amdgcn_readfirstlane((int)st.cur);
-                const uint16_t* list;
-                int L;
-                if constexpr (kTabu == MMAS_TABU_BITMASK) {
-                    gather_unvisited_block(tabu, n, ulist, &wl->counter);
-                    __syncthreads();
-                    L = __builtin_amdgcn_readfirstlane((int)wl->counter);
-                    list = ulist;
-                } else {
-                    L = __builtin_amdgcn_readfirstlane(st.L);
-                    list = tabu.list();
-                    if constexpr (kTabu == MMAS_TABU_LIST) tabu.L = L;  // the helpers' copy of the length
-                }
-                // by draw blocks while they are cheaper: a block costs about a
-                // Philox and four keys, a listed city a Philox and one key
-                const bool by_blocks = kTabu != MMAS_TABU_BITMASK && 46 * L > 25 * n;
-                unsigned long long mine;
-                if constexpr (kPher == MMAS_PHER_DENSE) {
-                    const DenseFactor wt{vw.choice_inv + (size_t)fcur * n};
-                    mine = by_blocks
-                               ? fallback_share_blocks(tabu, n, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw)
-                               : fallback_share(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw);
-                } else {
-                    const CandFactor wt{dist + (size_t)fcur * n, tmin_a, s.beta};
-                    mine = by_blocks
-                               ? fallback_share_blocks(tabu, n, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw)
-                               : fallback_share(list, L, wt, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane, wv, nw);
-                }
+                __syncthreads();
+                int L = 0;
+                if constexpr (kTabu != MMAS_TABU_BITMASK) L = tabu.L;
+                const unsigned long long mine =
+                    wide_share<kTabu, kPher>(vw, s, it, ant, k, cur, L, tabu, ulist, wl, tmin_a, lane, wv, nw);
                 if (lane == 0) wl->res[wv] = mine;
                 __syncthreads();
-                if (lead) {
-                    // the best over the waves (lanes 0 .. nw-1, one row): the
-                    // largest key code, then the largest ~city
-                    const unsigned long long r = lane < nw ? wl->res[lane] : 0ull;
-                    const uint32_t hi = (uint32_t)(r >> 32), lo = (uint32_t)r;
-                    const uint32_t mx = wave_max_u32<2>(hi);
-                    uint32_t best_lo;
-                    const uint64_t tied = __ballot(hi == mx && lane < nw);
-                    if (__popcll(tied) == 1)
-                        best_lo = (uint32_t)__builtin_amdgcn_readlane((int)lo, __ffsll((unsigned long long)tied) - 1);
-                    else
-                        best_lo = wave_max_u32<2>(hi == mx ? lo : 0u);
-                    next = mx ? ~best_lo : kNone;
-                }
-                // (the record, the counter and the list of this step are read
-                // before the last barrier; res is written again only after the
-                // next step's first barrier)
-            }
-            if (!lead) continue;
-            if (next >= (uint32_t)n) {
-                // unreachable with a validated instance: report it, and let
-                // every wave leave at the next step's record
-                if (lane == 0) atomicOr(&vw.state->flags, 8u);
-                stop = true;
-                if (k == n - 1) break;
-                continue;
+                // the best over the waves (lanes 0 .. nw-1, one row): the
+                // largest key code, then the largest ~city
+                const unsigned long long r = lane < nw ? wl->res[lane] : 0ull;
+                const uint32_t hi = (uint32_t)(r >> 32), lo = (uint32_t)r;
+                const uint32_t mx = wave_max_u32<2>(hi);
+                uint32_t best_lo;
+                const uint64_t tied = __ballot(hi == mx && lane < nw);
+                if (__popcll(tied) == 1)
+                    best_lo = (uint32_t)__builtin_amdgcn_readlane((int)lo, __ffsll((unsigned long long)tied) - 1);
+                else
+                    best_lo = wave_max_u32<2>(hi == mx ? lo : 0u);
+                next = mx ? ~best_lo : kNone;
+                // (the record, the counter and the list are read before the
+                // second barrier; res is written again only after the next
+                // fallback's first barrier)
             }
         } else if (next == kNone) {
             fb_steps += 1;
@@ -768,7 +778,18 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
             prev_last = (uint32_t)__builtin_amdgcn_readlane((int)tbuf, slot);
         }
     }
-    if (!lead) return;
+    if constexpr (kWide) {
+        // the end of the tour (or of an unreachable city): the helpers leave
+        if (lane == 0) {
+            WideStep st;
+            st.k = 0;
+            st.cur = 0u;
+            st.L = 0;
+            st.stop = 1;
+            wl->step = st;
+        }
+        __syncthreads();
+    }
     if (lane == 0) len += dist[(size_t)cur * n + start];  // closing edge
     len = wave_sum_i64(len);
     if (lane == 0) {
