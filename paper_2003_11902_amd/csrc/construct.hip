@@ -582,6 +582,80 @@ __device__ unsigned long long wide_share(const Views& vw, const Shape& s, uint32
     }
 }
 
+// The helper waves of a workgroup-wide ant: they wait at the barrier until
+// the leading wave posts a fallback (or the end of its tour), key their share
+// and post their best, so the steps without a fallback need no barrier.
+template <int kTabu, int kPher>
+__device__ void wide_helpers(const Views& vw, const Shape& s, uint32_t it, int ant, int lane, uint8_t* region,
+                             WideLds* wl, int wv, int nw) {
+    const int n = s.n;
+    typename TabuOf<kTabu>::type tabu;
+    tabu.attach(region + kDrawBytes + kScratchBytes, n);
+    uint16_t* ulist = reinterpret_cast<uint16_t*>(region + kDrawBytes + kScratchBytes + align16(4 * ((n + 31) / 32)));
+    float tmin_a = 0.0f;
+    if (kPher == MMAS_PHER_CANDIDATES) tmin_a = powi(vw.state->tau_min, s.alpha);
+    for (;;) {
+        __syncthreads();  // a posted fallback, or the end
+        const WideStep st = wl->step;
+        if (__builtin_amdgcn_readfirstlane(st.stop)) return;
+        const unsigned long long mine =
+            wide_share<kTabu, kPher>(vw, s, it, ant, __builtin_amdgcn_readfirstlane(st.k),
+                                     (uint32_t)__builtin_amdgcn_readfirstlane((int)st.cur),
+                                     __builtin_amdgcn_readfirstlane(st.L), tabu, ulist, wl, tmin_a, lane, wv, nw);
+        if (lane == 0) wl->res[wv] = mine;
+        __syncthreads();  // the results (read by the leading wave)
+    }
+}
+
+// The leading wave's side of a workgroup-wide fallback at step k from city
+// cur: posts it, keys its share with the helpers, and takes the best over
+// the waves (the largest key code, then the lowest city); kNone if none.
+template <int kTabu, int kPher, class T>
+__device__ uint32_t wide_lead_fallback(const Views& vw, const Shape& s, uint32_t it, int ant, int k, uint32_t cur,
+                                       T& tabu, uint16_t* ulist, WideLds* wl, float tmin_a, int lane, int nw) {
+    if (lane == 0) {
+        WideStep st;
+        st.k = k;
+        st.cur = cur;
+        st.L = 0;
+        if constexpr (kTabu != MMAS_TABU_BITMASK) st.L = tabu.L;
+        st.stop = 0;
+        wl->step = st;
+        if constexpr (kTabu == MMAS_TABU_BITMASK) wl->counter = 0u;
+    }
+    __syncthreads();
+    int L = 0;
+    if constexpr (kTabu != MMAS_TABU_BITMASK) L = tabu.L;
+    const unsigned long long mine = wide_share<kTabu, kPher>(vw, s, it, ant, k, cur, L, tabu, ulist, wl, tmin_a, lane, 0, nw);
+    if (lane == 0) wl->res[0] = mine;
+    __syncthreads();
+    // (the record, the counter and the list are read before the second
+    // barrier; res is written again only after the next fallback's first)
+    const unsigned long long r = lane < nw ? wl->res[lane] : 0ull;
+    const uint32_t hi = (uint32_t)(r >> 32), lo = (uint32_t)r;
+    const uint32_t mx = wave_max_u32<2>(hi);
+    uint32_t best_lo;
+    const uint64_t tied = __ballot(hi == mx && lane < nw);
+    if (__popcll(tied) == 1)
+        best_lo = (uint32_t)__builtin_amdgcn_readlane((int)lo, __ffsll((unsigned long long)tied) - 1);
+    else
+        best_lo = wave_max_u32<2>(hi == mx ? lo : 0u);
+    return mx ? ~best_lo : kNone;
+}
+
+// The end of the leading wave's tour: the helpers leave.
+__device__ void wide_lead_end(WideLds* wl, int lane) {
+    if (lane == 0) {
+        WideStep st;
+        st.k = 0;
+        st.cur = 0u;
+        st.L = 0;
+        st.stop = 1;
+        wl->step = st;
+    }
+    __syncthreads();
+}
+
 // One ant's tour (one wave64): start city, n - 1 selection steps, tour and
 // length stores. `region` is the ant's LDS region; rows 0..R-1 of the
 // candidate table are in LDS at tcand / tchc.
@@ -808,9 +882,12 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
 // test for it) inside chunks of 64 (one tour flush per chunk); the visited
 // test folds into the key code as a mask; and for cl <= 32 (kRows = 2) the
 // argmax reduces only the two rows that hold the list.
-template <int kTabu, int kPher, int kRows, int kG>
+// kWide: the wave leads a workgroup whose other waves share its fallbacks
+// (wide_helpers), nw waves in all.
+template <int kTabu, int kPher, int kRows, int kG, bool kWide = false>
 __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int ant, int lane, uint8_t* region,
-                               const uint16_t* tcand, const float* tchc, int R) {
+                               const uint16_t* tcand, const float* tchc, int R, WideLds* wl = nullptr,
+                               int nw = 1) {
     const int n = s.n, cl = s.cl;
     const uint64_t seed = s.seed;
     float* lnbuf = reinterpret_cast<float*>(region);
@@ -866,7 +943,10 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
         // (k laundered so that n - k is not kept as a 64-bit induction
         // variable on every step)
         int kk = k;
-        asm volatile("" : "+s"(kk));
+        if constexpr (kWide)
+            kk = __builtin_amdgcn_readfirstlane(kk);
+        else
+            asm volatile("" : "+s"(kk));
         fb_steps += 1;
         fb_nodes += n - kk;
         // (C-style casts: the only casts that change the address space)
@@ -875,7 +955,9 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
         const GlbPtr<const int32_t> drow =
             kPher == MMAS_PHER_DENSE ? nullptr : (GlbPtr<const int32_t>)(dist + (size_t)cur * n);
         uint32_t pick;
-        if constexpr (kTabu == MMAS_TABU_BITMASK)
+        if constexpr (kWide)
+            pick = wide_lead_fallback<kTabu, kPher>(vw, s, it, ant, kk, (uint32_t)cur, tabu, ulist, wl, tmin_a, lane, nw);
+        else if constexpr (kTabu == MMAS_TABU_BITMASK)
             pick = fallback_lone<kTabu, kPher>((LdsPtr<const uint16_t>)tabu.bits, (LdsPtr<uint16_t>)ulist, n - kk, n,
                                                irow, drow, tmin_a, s.beta, cl, seed, it, (uint32_t)ant, (uint32_t)k,
                                                lane);
@@ -1054,6 +1136,7 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
             flush(ke);
         }
     }
+    if constexpr (kWide) wide_lead_end(wl, lane);
     if (bad && lane == 0) atomicOr(&vw.state->flags, 8u);
     if (lane == 0) len += dist[(size_t)cur * n + start];  // closing edge
     len = wave_sum_i64(len);
@@ -1306,19 +1389,29 @@ __global__ __launch_bounds__(1024) void k_construct(Views vw, Shape s, uint32_t 
                                                 tchc, R);
 }
 
-// One ant per workgroup of several waves (construct_ant with kWide): the
-// table part of LDS, then the ant's region.
-template <int kTabu, int kPher>
+// One ant per workgroup of several waves: the leading wave takes the steps
+// as in the single colony (construct_lone), the others share its
+// fallbacks. LDS: the table part, then the ant's region. kRows, kG as for
+// k_construct.
+template <int kTabu, int kPher, int kRows = 4, int kG = 0>
 __global__ __launch_bounds__(1024) void k_construct_wide(Views vw, Shape s, uint32_t it, Lds lds) {
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ WideLds wl;
     const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int nw = (int)(blockDim.x >> 6);
     const int R = lds.rows;
     uint16_t* tcand = reinterpret_cast<uint16_t*>(smem);
     float* tchc = reinterpret_cast<float*>(smem + align16(R * s.cl * 2));
     if (R > 0) stage_table(vw, s.cl, R, tcand, tchc);
     __syncthreads();
-    construct_ant<kTabu, kPher, true>(vw, s, it, (int)blockIdx.x, lane, smem + lds.table_bytes, tcand, tchc, R, &wl);
+    uint8_t* region = smem + lds.table_bytes;
+    if (wave > 0) {
+        wide_helpers<kTabu, kPher>(vw, s, it, (int)blockIdx.x, lane, region, &wl, wave, nw);
+        return;
+    }
+    // the leading wave: the single-colony step, its fallbacks shared
+    construct_lone<kTabu, kPher, kRows, kG, true>(vw, s, it, (int)blockIdx.x, lane, region, tcand, tchc, R, &wl, nw);
 }
 
 // Without candidate lists, for small instances with SIMDs to spare: a team
@@ -1598,7 +1691,10 @@ hipError_t launch_wide(const Views& v, const Shape& s, uint32_t it, int waves, h
     lds.rows = rows;
     lds.table_bytes = align16(rows * s.cl * 2) + align16(rows * s.cl * 4);
     const size_t bytes = (size_t)lds.table_bytes + (size_t)per_ant;
-    auto kern = k_construct_wide<kTabu, kPher>;
+    auto kern = s.cl > 16 && s.cl <= 32 ? k_construct_wide<kTabu, kPher, 2, 8>
+                : s.cl > 8 && s.cl <= 16 ? k_construct_wide<kTabu, kPher, 2, 4>
+                : s.cl <= 32             ? k_construct_wide<kTabu, kPher, 2>
+                                         : k_construct_wide<kTabu, kPher, 4>;
     if (bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
