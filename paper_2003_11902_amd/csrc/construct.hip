@@ -656,28 +656,19 @@ __device__ void wide_lead_end(WideLds* wl, int lane) {
     __syncthreads();
 }
 
-// One ant's tour (one wave64): start city, n - 1 selection steps, tour and
-// length stores. `region` is the ant's LDS region; rows 0..R-1 of the
-// candidate table are in LDS at tcand / tchc.
-// With kWide the whole workgroup serves one ant: wave 0 takes the steps and
-// the other waves join it for every fallback (wl: the workgroup's WideLds).
-template <int kTabu, int kPher, bool kWide = false>
+// One ant's tour (one wave64, the batched kernel's step): start city, n - 1
+// selection steps, tour and length stores. `region` is the ant's LDS region;
+// rows 0..R-1 of the candidate table are in LDS at tcand / tchc.
+template <int kTabu, int kPher>
 __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int ant, int lane, uint8_t* region,
-                              const uint16_t* tcand, const float* tchc, int R, WideLds* wl = nullptr) {
+                              const uint16_t* tcand, const float* tchc, int R) {
     const int n = s.n, cl = s.cl;
     const uint64_t seed = s.seed;
-    // (wave-uniform: scalar branches between the leading wave and the helpers)
-    const int wv = kWide ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)) : 0;
-    const int nw = kWide ? (int)(blockDim.x >> 6) : 1;
-    const bool lead = wv == 0;
 
     // per-ant LDS: the draws of the next steps (256 floats), then the tabu
     float* lnbuf = reinterpret_cast<float*>(region);
     typename TabuOf<kTabu>::type tabu;
-    if (lead)
-        tabu.init(region + kDrawBytes + kScratchBytes, n, lane);
-    else
-        tabu.attach(region + kDrawBytes + kScratchBytes, n);
+    tabu.init(region + kDrawBytes + kScratchBytes, n, lane);
     uint16_t* ulist = reinterpret_cast<uint16_t*>(region + kDrawBytes + kScratchBytes + align16(4 * ((n + 31) / 32)));
 
     float tmin_a = 0.0f;
@@ -691,7 +682,7 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
     // start city: floor(x * n / 2^32) of draw (step 0, slot 0)
     const uint32_t x0 = draw_block(seed, it, (uint32_t)ant, 0u, 0u).w[0];
     const uint32_t start = (uint32_t)(((uint64_t)x0 * (uint64_t)n) >> 32);
-    if (lead) tabu.mark(start, lane);
+    tabu.mark(start, lane);
 
     // Candidate draws are generated ahead, S steps at a time: lane l computes
     // the Philox block of step k + l/G and slots 4(l%G)..4(l%G)+3 and stores
@@ -708,26 +699,6 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
     int64_t len = 0;
     int64_t fb_steps = 0, fb_nodes = 0;
     uint32_t cur = start;
-
-    if constexpr (kWide) {
-        if (!lead) {
-            // Helper waves serve the fallbacks only: they wait at the barrier
-            // until the leading wave posts one (or the end of its tour), so
-            // that the steps without a fallback need no barrier.
-            for (;;) {
-                __syncthreads();  // a posted fallback, or the end
-                const WideStep st = wl->step;
-                if (__builtin_amdgcn_readfirstlane(st.stop)) return;
-                const unsigned long long mine =
-                    wide_share<kTabu, kPher>(vw, s, it, ant, __builtin_amdgcn_readfirstlane(st.k),
-                                             (uint32_t)__builtin_amdgcn_readfirstlane((int)st.cur),
-                                             __builtin_amdgcn_readfirstlane(st.L), tabu, ulist, wl, tmin_a, lane, wv,
-                                             nw);
-                if (lane == 0) wl->res[wv] = mine;
-                __syncthreads();  // the results (read by the leading wave)
-            }
-        }
-    }
 
     for (int k = 1; k < n; ++k) {
         uint32_t next = kNone;
@@ -773,45 +744,7 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
             // and one code path is faster than two)
             next = wave_select_step<4>(code, node);
         }
-        if constexpr (kWide) {
-            if (__builtin_expect(next == kNone, 0)) {
-                // post the fallback; every wave keys its share of it
-                fb_steps += 1;
-                fb_nodes += n - k;
-                if (lane == 0) {
-                    WideStep st;
-                    st.k = k;
-                    st.cur = cur;
-                    st.L = 0;
-                    if constexpr (kTabu != MMAS_TABU_BITMASK) st.L = tabu.L;
-                    st.stop = 0;
-                    wl->step = st;
-                    if constexpr (kTabu == MMAS_TABU_BITMASK) wl->counter = 0u;
-                }
-                __syncthreads();
-                int L = 0;
-                if constexpr (kTabu != MMAS_TABU_BITMASK) L = tabu.L;
-                const unsigned long long mine =
-                    wide_share<kTabu, kPher>(vw, s, it, ant, k, cur, L, tabu, ulist, wl, tmin_a, lane, wv, nw);
-                if (lane == 0) wl->res[wv] = mine;
-                __syncthreads();
-                // the best over the waves (lanes 0 .. nw-1, one row): the
-                // largest key code, then the largest ~city
-                const unsigned long long r = lane < nw ? wl->res[lane] : 0ull;
-                const uint32_t hi = (uint32_t)(r >> 32), lo = (uint32_t)r;
-                const uint32_t mx = wave_max_u32<2>(hi);
-                uint32_t best_lo;
-                const uint64_t tied = __ballot(hi == mx && lane < nw);
-                if (__popcll(tied) == 1)
-                    best_lo = (uint32_t)__builtin_amdgcn_readlane((int)lo, __ffsll((unsigned long long)tied) - 1);
-                else
-                    best_lo = wave_max_u32<2>(hi == mx ? lo : 0u);
-                next = mx ? ~best_lo : kNone;
-                // (the record, the counter and the list are read before the
-                // second barrier; res is written again only after the next
-                // fallback's first barrier)
-            }
-        } else if (next == kNone) {
+        if (next == kNone) {
             fb_steps += 1;
             fb_nodes += n - k;
             const int cap = list_cap(s);
@@ -851,18 +784,6 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
             }
             prev_last = (uint32_t)__builtin_amdgcn_readlane((int)tbuf, slot);
         }
-    }
-    if constexpr (kWide) {
-        // the end of the tour (or of an unreachable city): the helpers leave
-        if (lane == 0) {
-            WideStep st;
-            st.k = 0;
-            st.cur = 0u;
-            st.L = 0;
-            st.stop = 1;
-            wl->step = st;
-        }
-        __syncthreads();
     }
     if (lane == 0) len += dist[(size_t)cur * n + start];  // closing edge
     len = wave_sum_i64(len);
