@@ -1200,7 +1200,11 @@ __device__ void construct_pair(const Views& vw, const Shape& s, uint32_t it, int
             const int e = cur_l * cl + lr;
             uint32_t node;
             float w;
-            if (R == 0 || cur_l >= R) {
+            if (R == 0) {
+                // no table (a wave-uniform test, so no exec-mask bookkeeping)
+                node = glb_cand[e];
+                w = glb_chc[e];
+            } else if (cur_l >= R) {
                 node = glb_cand[e];
                 w = glb_chc[e];
             } else {
@@ -1246,8 +1250,19 @@ __device__ void construct_pair(const Views& vw, const Shape& s, uint32_t it, int
             bad |= (nextA >= (uint32_t)n) | (nextB >= (uint32_t)n);
             nextA = nextA < (uint32_t)n ? nextA : 0u;
             nextB = nextB < (uint32_t)n ? nextB : 0u;
-            tabA.mark(nextA, lane);
-            if (hasB) tabB.mark(nextB, lane ^ 32);
+            if constexpr (kTabu == MMAS_TABU_BITMASK) {
+                // both marks in one LDS OR issued by every lane: lane 0 sets
+                // A's bit, lane 32 B's (when B is there), the others OR zero
+                // into their own word of the draw buffer
+                const uint32_t nx = h ? nextB : nextA;
+                const bool setter = hl == 0 && (h == 0 || hasB);
+                uint32_t* word = setter ? (h ? tabB.bits : tabA.bits) + (nx >> 5)
+                                        : reinterpret_cast<uint32_t*>(lnbuf) + hl;
+                atomicOr(word, setter ? 1u << (nx & 31u) : 0u);
+            } else {
+                tabA.mark(nextA, lane);
+                if (hasB) tabB.mark(nextB, lane ^ 32);
+            }
             if (hl == (k & 31)) tbuf = h ? nextB : nextA;
             curA = __builtin_amdgcn_readfirstlane((int)nextA);
             curB = __builtin_amdgcn_readfirstlane((int)nextB);
