@@ -162,6 +162,10 @@ __global__ __launch_bounds__(1024) void k_two_opt(Views vw, Shape s, const int32
         const uint16_t* s_list = s_lists[par];
 
         __syncthreads();  // the list, the tour, positions, lengths and bits of this round
+        // (the list entries are read beside the count: one LDS round trip)
+        const int g = t >> lg, rl = t & (gs - 1);
+        const int a_l = s_list[g < kListCap ? g : 0];
+        const int le_l = s_list[lane];
         const int count = __builtin_amdgcn_readfirstlane(s_count[par]);
         if (count == 0) break;
         if (rounds > max_rounds) {
@@ -169,15 +173,14 @@ __global__ __launch_bounds__(1024) void k_two_opt(Views vw, Shape s, const int32
             return;
         }
         const int ev = min(count, E);
-        const int le = (wave <= merge_wave && lane < count) ? (int)s_list[lane] : 0;  // the list, one entry a lane
+        const int le = lane < count ? le_l : 0;  // the list, one entry a lane (used by waves 0 and 1)
 
         // ---- evaluate every candidate move of the first ev listed cities ----
-        const int g = t >> lg, rl = t & (gs - 1);
         const bool pred_dir = rl >= k;
         bool ok = false;
         int a = 0, a1 = 0, c = 0, c1 = 0, dac = 0, da1c1 = 0, pa = 0, pc = 0, fl = 0;
         if (g < ev && rl < 2 * k) {
-            a = s_list[g];
+            a = a_l;
             const int r = pred_dir ? rl - k : rl;
             if (a != ca) {  // the list often starts where the last one did
                 cc = nn[(size_t)a * k + r];
