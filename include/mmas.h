@@ -105,7 +105,10 @@ typedef struct mmas_device_state {
                           non-positive off the diagonal (set-up); 8: a
                           construction step found no city (never expected);
                           16: a 2-opt search hit its round limit (never
-                          expected; that ant's tour is left as it was) */
+                          expected; that ant's tour is left as it was);
+                          32: a construction wave gave up waiting for its
+                          draw helper wave (never expected; that tour is
+                          void) */
     uint32_t updates;  /* number of completed updates */
 } mmas_device_state;
 
@@ -177,7 +180,10 @@ mmas_status mmas_construct(mmas_ctx* ctx, uint32_t iteration);
  * per ant); 0 (default): several only where the all-city fallback dominates
  * (n >= 8192: the largest power of two up to 16 such that ants x waves fit
  * the GPU's SIMDs once; no candidate list with the compact or list tabu and
- * n >= 512: 4), else 1. EINVAL for other values. */
+ * n >= 512: 4), else 1; and where that is one wave with 9 <= cand_len <= 32
+ * and at most as many ants as the GPU has SIMDs, a second wave per ant
+ * computes the steps' draws ahead into LDS (a draw helper; at most 8 ants per
+ * workgroup then). 1 = the ant's wave alone. EINVAL for other values. */
 mmas_status mmas_set_launch(mmas_ctx* ctx, int32_t ants_per_block, int32_t table_rows, int32_t lanes_per_ant,
                             int32_t waves_per_ant);
 

@@ -440,19 +440,30 @@ struct WideLds {
 };
 
 // The unvisited cities of a bitmask tabu gathered by the whole workgroup
-// (thread t takes words t, t + threads, ...); `counter` is 0 on entry.
+// (thread t takes words t, t + threads, ...): a wave places its words' cities
+// by a prefix sum of their counts and claims room for all of them with one
+// LDS atomic; `counter` is 0 on entry.
 __device__ void gather_unvisited_block(const BitmaskTabu& tabu, int n, uint16_t* list, uint32_t* counter) {
     const int words = (n + 31) >> 5;
-    for (int wi = threadIdx.x; wi < words; wi += blockDim.x) {
-        uint32_t fr = ~tabu.bits[wi];
-        if (wi == words - 1 && (n & 31)) fr &= (1u << (n & 31)) - 1u;
-        if (fr) {
-            int p = (int)atomicAdd(counter, (uint32_t)__popc(fr));
-            while (fr) {
-                const int b = __ffs(fr) - 1;
-                fr &= fr - 1u;
-                list[p++] = (uint16_t)(wi * 32 + b);
-            }
+    const int lane = (int)(threadIdx.x & 63);
+    for (int w0 = (int)(threadIdx.x & ~63u); w0 < words; w0 += (int)blockDim.x) {
+        const int wi = w0 + lane;
+        uint32_t fr = 0u;
+        if (wi < words) {
+            fr = ~tabu.bits[wi];
+            if (wi == words - 1 && (n & 31)) fr &= (1u << (n & 31)) - 1u;
+        }
+        const int cnt = __popc(fr);
+        const int incl = wave_incl_scan(cnt, lane);
+        const int tot = __builtin_amdgcn_readlane(incl, 63);
+        if (tot == 0) continue;
+        uint32_t base = 0u;
+        if (lane == 0) base = atomicAdd(counter, (uint32_t)tot);
+        int p = __builtin_amdgcn_readfirstlane((int)base) + incl - cnt;
+        while (fr) {
+            const int b = __ffs(fr) - 1;
+            fr &= fr - 1u;
+            list[p++] = (uint16_t)(wi * 32 + b);
         }
     }
 }
@@ -656,6 +667,60 @@ __device__ void wide_lead_end(WideLds* wl, int lane) {
     __syncthreads();
 }
 
+// ---- the draw helper of a single-colony ant --------------------------------
+//
+// A second wave per ant computes the draws (Philox blocks and logarithms) of
+// each group of S = 64 / G steps into one of two LDS buffers, a group ahead
+// of the ant's wave, which then only reads them. Two counters in LDS hand
+// the buffers over: groups written (by the helper) and groups read (by the
+// ant's wave); the helper writes group g once group g - 2 is read. Waits are
+// bounded: past the limit the ant's wave flags the tour (state flag 32) and
+// the helper leaves, so no wave can wait for ever.
+constexpr size_t kHelpBytes = kDrawBytes + 16;  // second draw buffer, then the two counters
+constexpr int kHelpSpins = 1 << 24;              // sleeps of 64 clocks before a wait gives up
+
+// waits until the LDS counter c reaches `want`; false if it gave up
+__device__ __forceinline__ bool wait_count(const int* c, int want) {
+    const LdsPtr<volatile const int> vc = (LdsPtr<volatile const int>)c;
+    for (int spins = 0; spins < kHelpSpins; ++spins) {
+        if (__builtin_amdgcn_readfirstlane(*vc) >= want) {
+            asm volatile("" ::: "memory");
+            return true;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return false;
+}
+
+__device__ __forceinline__ void post_count(int* c, int v) {
+    asm volatile("" ::: "memory");
+    *(LdsPtr<volatile int>)c = v;
+}
+
+// The helper wave of ant `ant`: buffers buf0 / buf1 (256 floats each, laid
+// out as the single colony's draw buffer), counters cnt[0] (groups written)
+// and cnt[1] (groups read).
+template <int kG>
+__device__ void draw_helper(const Shape& s, uint32_t it, int ant, int lane, float* buf0, float* buf1, int* cnt) {
+    constexpr int gsh = kG == 1 ? 0 : kG == 2 ? 1 : kG == 4 ? 2 : kG == 8 ? 3 : 4;
+    constexpr int S = kWave >> gsh;
+    const int groups = (s.n + S - 1) / S;
+    for (int g = 0; g < groups; ++g) {
+        const Words4 b = draw_block(s.seed, it, (uint32_t)ant, (uint32_t)(g * S + (lane >> gsh)),
+                                    (uint32_t)(4 * (lane & (kG - 1))));
+        float4 lv;
+        lv.x = log_u01(u01(b.w[0]));
+        lv.y = log_u01(u01(b.w[1]));
+        lv.z = log_u01(u01(b.w[2]));
+        lv.w = log_u01(u01(b.w[3]));
+        // the buffer of group g held group g - 2
+        if (g >= 2 && !wait_count(cnt + 1, g - 1)) return;
+        *reinterpret_cast<float4*>(((g & 1) ? buf1 : buf0) + 4 * lane) = lv;
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the draws are in LDS before the count
+        post_count(cnt, g + 1);
+    }
+}
+
 // One ant's tour (one wave64, the batched kernel's step): start city, n - 1
 // selection steps, tour and length stores. `region` is the ant's LDS region;
 // rows 0..R-1 of the candidate table are in LDS at tcand / tchc.
@@ -804,11 +869,13 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
 // test folds into the key code as a mask; and for cl <= 32 (kRows = 2) the
 // argmax reduces only the two rows that hold the list.
 // kWide: the wave leads a workgroup whose other waves share its fallbacks
-// (wide_helpers), nw waves in all.
-template <int kTabu, int kPher, int kRows, int kG, bool kWide = false>
+// (wide_helpers), nw waves in all. kHelp (kG > 0): a draw helper wave
+// (draw_helper) fills the draw buffers; `help` is its part of the region
+// (second buffer, counters).
+template <int kTabu, int kPher, int kRows, int kG, bool kWide = false, bool kHelp = false>
 __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int ant, int lane, uint8_t* region,
                                const uint16_t* tcand, const float* tchc, int R, WideLds* wl = nullptr,
-                               int nw = 1) {
+                               int nw = 1, uint8_t* help = nullptr) {
     const int n = s.n, cl = s.cl;
     const uint64_t seed = s.seed;
     float* lnbuf = reinterpret_cast<float*>(region);
@@ -822,7 +889,7 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
     const LdsPtr<const float> lds_chc = (LdsPtr<const float>)tchc;
     const GlbPtr<const uint16_t> glb_cand = (GlbPtr<const uint16_t>)vw.cand;
     const GlbPtr<const float> glb_chc = (GlbPtr<const float>)vw.chc_inv;  // reciprocals
-    const LdsPtr<const float> lds_ln = (LdsPtr<const float>)lnbuf;
+    LdsPtr<const float> lds_ln = (LdsPtr<const float>)lnbuf;
 
     const uint32_t x0 = draw_block(seed, it, (uint32_t)ant, 0u, 0u).w[0];
     const int start = __builtin_amdgcn_readfirstlane((int)(((uint64_t)x0 * (uint64_t)n) >> 32));
@@ -858,6 +925,7 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
     int64_t fb_steps = 0, fb_nodes = 0;
     int cur = start;
     bool bad = false;
+    bool bad_help = false;  // a wait for the draw helper gave up
 
     // the all-city fallback of step k from city cur (rare with a list)
     auto fallback = [&](int k) -> uint32_t {
@@ -993,6 +1061,22 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
             advance(fallback(k), k);
             flush(k + 1);
         }
+    } else if constexpr (kG > 0 && kHelp) {
+        // draws from the helper wave: group g in buffer g & 1
+        const LdsPtr<const float> buf0 = (LdsPtr<const float>)lnbuf;
+        const LdsPtr<const float> buf1 = (LdsPtr<const float>)reinterpret_cast<float*>(help);
+        int* cnt = reinterpret_cast<int*>(help + kDrawBytes);
+        constexpr int S = kWave / kG;
+        load_row(cur);
+        int g = 0;
+        for (int k0 = 0; k0 < n; k0 += S, ++g) {
+            if (!bad_help) bad_help = !wait_count(cnt, g + 1);  // (after one timeout, no more waits)
+            lds_ln = (g & 1) ? buf1 : buf0;
+            const int ke = k0 + S < n ? k0 + S : n;
+            steps_plain(k0, k0 > 0 ? k0 : 1, ke);
+            post_count(cnt + 1, g + 1);  // after the group's last read of its buffer
+            flush(ke);
+        }
     } else if constexpr (kG > 0) {
         load_row(cur);
         // Draws computed one group ahead, spread over the steps of the group
@@ -1059,6 +1143,7 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
     }
     if constexpr (kWide) wide_lead_end(wl, lane);
     if (bad && lane == 0) atomicOr(&vw.state->flags, 8u);
+    if (bad_help && lane == 0) atomicOr(&vw.state->flags, 32u);
     if (lane == 0) len += dist[(size_t)cur * n + start];  // closing edge
     len = wave_sum_i64(len);
     if (lane == 0) {
@@ -1301,8 +1386,10 @@ __device__ void construct_pair(const Views& vw, const Shape& s, uint32_t it, int
 // kRows: 16-lane rows the argmax of a one-ant-per-wave step reduces (2 for
 // cl <= 32, else 4); kG: 4-slot draw groups per step when fixed (4 for
 // 9 <= cl <= 16, 8 for 17 <= cl <= 32: the draws are then pipelined), else 0.
-// Both unused with two ants per wave.
-template <int kTabu, int kPher, bool kPair, int kRows = 4, int kG = 0>
+// Both unused with two ants per wave. kHelp (one ant per wave, kG > 0): the
+// workgroup has a draw helper wave per ant (waves apb .. 2 apb - 1 for the
+// ants of waves 0 .. apb - 1); each region ends with the helper's part.
+template <int kTabu, int kPher, bool kPair, int kRows = 4, int kG = 0, bool kHelp = false>
 __global__ __launch_bounds__(1024) void k_construct(Views vw, Shape s, uint32_t it, int ants_per_block, Lds lds) {
     extern __shared__ __align__(16) uint8_t smem[];
     const int lane = threadIdx.x & 63;
@@ -1310,13 +1397,30 @@ __global__ __launch_bounds__(1024) void k_construct(Views vw, Shape s, uint32_t 
     const int R = lds.rows;
     uint16_t* tcand = reinterpret_cast<uint16_t*>(smem);
     float* tchc = reinterpret_cast<float*>(smem + align16(R * s.cl * 2));
-    if (R > 0) {
-        stage_table(vw, s.cl, R, tcand, tchc);
-        __syncthreads();
-    }
-    const int ant = blockIdx.x * ants_per_block + (kPair ? 2 * wave : wave);
-    if (ant >= s.ants) return;  // whole waves leave together
     uint8_t* regions = smem + lds.table_bytes;
+    if (R > 0) stage_table(vw, s.cl, R, tcand, tchc);
+    if constexpr (kHelp) {
+        // both counters of every ant start at 0
+        if ((int)threadIdx.x < ants_per_block)
+            *reinterpret_cast<int2*>(regions + (size_t)(threadIdx.x + 1) * lds.per_ant - kHelpBytes + kDrawBytes) =
+                make_int2(0, 0);
+    }
+    if (R > 0 || kHelp) __syncthreads();
+    const bool helper = kHelp && wave >= ants_per_block;
+    const int aw = helper ? wave - ants_per_block : wave;
+    const int ant = blockIdx.x * ants_per_block + (kPair ? 2 * aw : aw);
+    if (ant >= s.ants) return;  // whole waves leave together
+    if constexpr (kHelp) {
+        uint8_t* region = regions + (size_t)aw * lds.per_ant;
+        uint8_t* help = region + lds.per_ant - kHelpBytes;
+        if (helper)
+            draw_helper<kG>(s, it, ant, lane, reinterpret_cast<float*>(region), reinterpret_cast<float*>(help),
+                            reinterpret_cast<int*>(help + kDrawBytes));
+        else
+            construct_lone<kTabu, kPher, kRows, kG, false, true>(vw, s, it, ant, lane, region, tcand, tchc, R,
+                                                                 nullptr, 1, help);
+        return;
+    }
     if constexpr (kPair)
         construct_pair<kTabu, kPher>(vw, s, it, ant, ant + 1 < s.ants, lane, regions + (size_t)(2 * wave) * lds.per_ant,
                                      regions + (size_t)(2 * wave + 1) * lds.per_ant, tcand, tchc, R);
@@ -1544,11 +1648,17 @@ hipError_t launch_t(const Views& v, const Shape& s0, uint32_t it, hipStream_t st
     // lists every unvisited city in one pass
     Shape s = s0;
     s.list_cap = s.n;
-    const int per_ant = (int)construct_lds_per_ant(s);
+    // a draw helper wave per ant (one ant per wave with pipelined draws) by
+    // default while every ant's wave has a SIMD of its own, which the helper
+    // then shares; not with one wave per ant asked for
+    const bool help = !kPair && kG > 0 && s.construct_waves == 0 &&
+                      s.ants <= device_attr(g_simds, hipDeviceAttributeMultiprocessorCount, 4, 0);
+    const int per_ant = (int)construct_lds_per_ant(s) + (help ? (int)kHelpBytes : 0);
     const int budget = max_lds_per_block();
     int apb = s.ants_per_block > 0 ? s.ants_per_block : 4;
     const int step = kPair ? 2 : 1;  // ants per wave
     if (apb < step) apb = step;
+    if (help && apb > 8) apb = 8;  // two waves per ant, at most 16 a workgroup
     while (apb > step && per_ant * apb > budget) apb -= step;
     if (per_ant * apb > budget) return hipErrorInvalidValue;
     // as many rows of the candidate table as fit next to the ants' regions;
@@ -1559,7 +1669,7 @@ hipError_t launch_t(const Views& v, const Shape& s0, uint32_t it, hipStream_t st
     int lds_wg = budget;
     const int cus = device_attr(g_cus, hipDeviceAttributeMultiprocessorCount, 1, 0);
     if (cus > 0 && s.table_rows < 0) {
-        const int waves = apb / step;
+        const int waves = apb / step * (help ? 2 : 1);
         int per_cu = (blocks + cus - 1) / cus;
         const int most = waves < 32 ? 32 / waves : 1;  // eight waves per SIMD
         if (per_cu > most) per_cu = most;
@@ -1580,11 +1690,14 @@ hipError_t launch_t(const Views& v, const Shape& s0, uint32_t it, hipStream_t st
     lds.table_bytes = align16(rows * s.cl * 2) + align16(rows * s.cl * 4);
     const size_t bytes = (size_t)lds.table_bytes + (size_t)apb * per_ant;
     auto kern = k_construct<kTabu, kPher, kPair, kRows, kG>;
+    if constexpr (!kPair && kG > 0) {
+        if (help) kern = k_construct<kTabu, kPher, false, kRows, kG, true>;
+    }
     if (bytes > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
     }
-    kern<<<blocks, 64 * (apb / step), bytes, st>>>(v, s, it, apb, lds);
+    kern<<<blocks, 64 * (apb / step) * (help ? 2 : 1), bytes, st>>>(v, s, it, apb, lds);
     return hipGetLastError();
 }
 

@@ -219,6 +219,12 @@ def test_error_paths(gpu):
     ((8, -1, 32, 0), "list", "candidates", 16, 64),
     ((0, -1, 64, 8), "list", "dense", 0, 20),
     ((0, 0, 64, 0), "bitmask", "dense", 32, 101),  # waves from the ant count
+    ((2, -1, 64, 0), "list", "candidates", 12, 63),  # a draw helper wave per ant; the last workgroup has one ant
+    ((8, 0, 64, 0), "compact", "dense", 20, 101),  # eight ants and eight helpers a workgroup
+    ((16, -1, 64, 0), "bitmask", "dense", 32, 101),  # sixteen asked for: eight with helpers
+    ((0, 0, 64, 4), "bitmask", "dense", 16, 101),  # cl 9..16, rows from global memory
+    ((0, 100, 64, 2), "compact", "dense", 9, 33),
+    ((0, 0, 64, 8), "list", "candidates", 12, 64),
 ])
 def test_launch_shapes_match_oracle(gpu, launch, tabu, pher, cl, ants):
     """Ants per workgroup, LDS table rows, two ants per wave (32 lanes each)
