@@ -275,6 +275,20 @@ __device__ __forceinline__ uint32_t fallback_bitmask(const BitmaskTabu& tabu, in
     return wave_select<4>(bcode, bnode);
 }
 
+// A wave's best (key code, lowest city) packed so that the larger value is
+// the better one; 0 if the wave saw no city.
+__device__ __forceinline__ unsigned long long share_result(uint32_t bcode, uint32_t bnode) {
+    const uint32_t bc = wave_max_u32<4>(bcode);
+    if (bc == 0u) return 0ull;
+    const uint64_t tied = __ballot(bcode == bc);
+    uint32_t node;
+    if (__popcll(tied) == 1)
+        node = (uint32_t)__builtin_amdgcn_readlane((int)bnode, __ffsll((unsigned long long)tied) - 1);
+    else
+        node = wave_min_u32<4>(bcode == bc ? bnode : kNone);
+    return ((unsigned long long)bc << 32) | (unsigned long long)(~node);
+}
+
 // The all-node fallback of the single-colony kernel, outlined (it is rare
 // with a list, and one copy serves every step of the unrolled step loop):
 // the same keys and winner as fallback_bitmask / fallback_list, but with the
@@ -422,6 +436,106 @@ __device__ __attribute__((noinline)) uint32_t fallback_lone(LdsPtr<const uint16_
     return wave_select<4>(bcode, bnode);
 }
 
+// The same fallback for the compact and list tabus, split between `parts`
+// waves that call this with part = 0 .. parts - 1 and the same other
+// arguments (a single-colony ant's wave and its draw helper): each keys its
+// share (alternate rounds of blocks, or alternate 64-entry chunks of the
+// tabu's list, a round holding up to four) and the best of the parts'
+// results is the winner. Returns this part's best as share_result packs it.
+template <int kTabu, int kPher>
+__device__ __attribute__((noinline)) unsigned long long fallback_half(
+    LdsPtr<const uint16_t> tabu_v, LdsPtr<const uint16_t> list_v, int L_v, int n_v, GlbPtr<const float> irow_v,
+    GlbPtr<const int32_t> drow_v, float tmin_a_v, int beta_v, int cl_v, uint64_t seed_v, uint32_t it_v,
+    uint32_t ant_v, uint32_t step_v, int part_v, int parts_v, int lane) {
+    static_assert(kTabu != MMAS_TABU_BITMASK, "the tabu keeps the list of unvisited cities");
+    const LdsPtr<const uint16_t> tabu = (LdsPtr<const uint16_t>)uni((uint32_t)(uintptr_t)tabu_v);
+    const LdsPtr<const uint16_t> list = (LdsPtr<const uint16_t>)uni((uint32_t)(uintptr_t)list_v);
+    const GlbPtr<const float> irow = (GlbPtr<const float>)uni((uint64_t)(uintptr_t)irow_v);
+    const GlbPtr<const int32_t> drow = (GlbPtr<const int32_t>)uni((uint64_t)(uintptr_t)drow_v);
+    const int L = uni(L_v);
+    const int n = uni(n_v), beta = uni(beta_v), cl = uni(cl_v);
+    const float tmin_a = uni(tmin_a_v);
+    const uint64_t seed = uni(seed_v);
+    const uint32_t it = uni(it_v), ant = uni(ant_v), step = uni(step_v);
+    const int part = uni(part_v), parts = uni(parts_v);
+    auto factor = [&](uint32_t v) -> float {
+        if constexpr (kPher == MMAS_PHER_DENSE)
+            return irow[v];
+        else
+            return 1.0f / (tmin_a * heur_from_dist(drow[v], beta));
+    };
+    const int b_lo = cl >> 2, nb = ((cl + n - 1) >> 2) - b_lo + 1;  // blocks holding slots cl .. cl + n - 1
+    const int span = kWave * parts;
+    const int rounds_b = (nb + span - 1) / span, per_lane = (L + span - 1) / span;
+    uint32_t bcode = 0u, bnode = kNone;
+    if (225 * rounds_b < 85 * per_lane) {
+        for (int b0 = b_lo + part * kWave; b0 < b_lo + nb; b0 += span) {
+            const int b = b0 + lane;
+            uint32_t v[4];
+            bool ok[4];
+            float f[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = 4 * b + j - cl;
+                ok[j] = b < b_lo + nb && c >= 0 && c < n;
+                v[j] = ok[j] ? (uint32_t)c : 0u;
+            }
+            // the tabu and factor loads go out before the draws
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const bool seen = kTabu == MMAS_TABU_COMPACT ? tabu[v[j]] > v[j] : (int)tabu[n + v[j]] >= L;
+                ok[j] = ok[j] & !seen;
+                f[j] = factor(v[j]);
+            }
+            const Words4 blk = draw_block(seed, it, ant, step, (uint32_t)(4 * b));
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float key = log_u01(u01(blk.w[j])) * f[j];
+                keep_best(ok[j] ? ord_key(key) : 0u, v[j], bcode, bnode);
+            }
+        }
+        return share_result(bcode, bnode);
+    }
+    // By list entries (the tabu's list of the L unvisited cities), in chunks
+    // of 64: this part takes chunks part, part + parts, ...
+    const int c0 = part, cs = parts;
+    // U chunks a round (U <= 4): the factor loads go out before the draws
+    // and their logarithms
+    auto key_round = [&](auto u_tag, int c) {
+        constexpr int U = decltype(u_tag)::value;
+        uint32_t v[U];
+        float f[U];
+        bool ok[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = (c + u * cs) * kWave + lane;
+            ok[u] = i < L;
+            v[u] = list[ok[u] ? i : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) f[u] = factor(v[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t slot = (uint32_t)cl + v[u];
+            const Words4 blk = draw_block(seed, it, ant, step, slot);
+            const float key = log_u01(u01(pick_word(blk, slot & 3u))) * f[u];
+            const uint32_t code = ok[u] ? ord_key(key) : 0u;
+            keep_best(code, v[u], bcode, bnode);
+        }
+    };
+    const int chunks = (L + kWave - 1) / kWave;
+    int left = chunks > c0 ? (chunks - c0 + cs - 1) / cs : 0;  // this part's chunks
+    int c = c0;
+    for (; left >= 4; left -= 4, c += 4 * cs) key_round(std::integral_constant<int, 4>{}, c);
+    if (left == 3)
+        key_round(std::integral_constant<int, 3>{}, c);
+    else if (left == 2)
+        key_round(std::integral_constant<int, 2>{}, c);
+    else if (left == 1)
+        key_round(std::integral_constant<int, 1>{}, c);
+    return share_result(bcode, bnode);
+}
+
 // ---- several waves per ant: the fallback shared by the workgroup ----------
 
 // What the leading wave (the one taking the steps) hands to the helper waves
@@ -468,19 +582,6 @@ __device__ void gather_unvisited_block(const BitmaskTabu& tabu, int n, uint16_t*
     }
 }
 
-// A wave's best (key code, lowest city) packed so that the larger value is
-// the better one; 0 if the wave saw no city.
-__device__ __forceinline__ unsigned long long share_result(uint32_t bcode, uint32_t bnode) {
-    const uint32_t bc = wave_max_u32<4>(bcode);
-    if (bc == 0u) return 0ull;
-    const uint64_t tied = __ballot(bcode == bc);
-    uint32_t node;
-    if (__popcll(tied) == 1)
-        node = (uint32_t)__builtin_amdgcn_readlane((int)bnode, __ffsll((unsigned long long)tied) - 1);
-    else
-        node = wave_min_u32<4>(bcode == bc ? bnode : kNone);
-    return ((unsigned long long)bc << 32) | (unsigned long long)(~node);
-}
 
 // This wave's share of a workgroup-wide fallback (entries wave*64 + lane,
 // then every 64*waves): its best (key code, lowest city), packed so that the
@@ -671,19 +772,47 @@ __device__ void wide_lead_end(WideLds* wl, int lane) {
 //
 // A second wave per ant computes the draws (Philox blocks and logarithms) of
 // each group of S = 64 / G steps into one of two LDS buffers, a group ahead
-// of the ant's wave, which then only reads them. Two counters in LDS hand
-// the buffers over: groups written (by the helper) and groups read (by the
-// ant's wave); the helper writes group g once group g - 2 is read. Waits are
-// bounded: past the limit the ant's wave flags the tour (state flag 32) and
-// the helper leaves, so no wave can wait for ever.
-constexpr size_t kHelpBytes = kDrawBytes + 16;  // second draw buffer, then the two counters
-constexpr int kHelpSpins = 1 << 24;              // sleeps of 64 clocks before a wait gives up
+// of the ant's wave, which then only reads them; with the compact tabu
+// (kHelpShare) it also keys half of every all-city fallback (fallback_half's
+// part 1) while the ant's wave keys the other half. Counters in LDS hand the
+// buffers and the fallbacks over: the helper writes group g once group
+// g - 2 is read, and serves a posted fallback whenever it waits. Waits are bounded: past the limit the ant's
+// wave flags the tour (state flag 32) and keys the rest alone, and the
+// helper leaves, so no wave can wait for ever.
+struct HelpLds {
+    int made;                // draw groups written (helper)
+    int read;                // draw groups read (ant's wave)
+    int req;                 // fallbacks posted (ant's wave)
+    int done;                // fallbacks whose part 1 is keyed (helper)
+    int k;                   // the posted fallback: step,
+    uint32_t cur;            // current city,
+    int L;                   // unvisited cities,
+    int stop;                // and 1 once the tour is done (the helper leaves)
+    unsigned long long res;  // part 1's best (share_result) of fallback `done`
+    int pad[2];
+};
+static_assert(sizeof(HelpLds) == 48, "16-byte multiple");
+constexpr size_t kHelpBytes = kDrawBytes + sizeof(HelpLds);  // second draw buffer, then the counters
+constexpr int kHelpSpins = 1 << 24;                          // sleeps of 64 clocks before a wait gives up
+// The tabus whose fallbacks the helper shares: measured at n = 1002, the
+// shared fallback made the compact tabu's construction 4 % faster and the
+// bitmask and list tabus' 1-3 % slower (the bitmask keeps its one-pass
+// listing, the list tabu's fallbacks are short).
+template <int kTabu>
+constexpr bool kHelpShare = kTabu == MMAS_TABU_COMPACT;
+
+__device__ __forceinline__ int lds_get(const int* c) {
+    return __builtin_amdgcn_readfirstlane(*(LdsPtr<volatile const int>)c);
+}
+__device__ __forceinline__ void lds_put(int* c, int v) {
+    asm volatile("" ::: "memory");
+    *(LdsPtr<volatile int>)c = v;
+}
 
 // waits until the LDS counter c reaches `want`; false if it gave up
 __device__ __forceinline__ bool wait_count(const int* c, int want) {
-    const LdsPtr<volatile const int> vc = (LdsPtr<volatile const int>)c;
     for (int spins = 0; spins < kHelpSpins; ++spins) {
-        if (__builtin_amdgcn_readfirstlane(*vc) >= want) {
+        if (lds_get(c) >= want) {
             asm volatile("" ::: "memory");
             return true;
         }
@@ -692,19 +821,73 @@ __device__ __forceinline__ bool wait_count(const int* c, int want) {
     return false;
 }
 
-__device__ __forceinline__ void post_count(int* c, int v) {
-    asm volatile("" ::: "memory");
-    *(LdsPtr<volatile int>)c = v;
+// Part `part` of two of the all-city fallback of step k from city cur with
+// L unvisited cities, on the list of the ant's tabu (compact or list).
+template <int kTabu, int kPher, class T>
+__device__ __forceinline__ unsigned long long half_part(const Views& vw, const Shape& s, uint32_t it, int ant, int k,
+                                                        uint32_t cur, int L, const T& tabu, float tmin_a, int part,
+                                                        int lane) {
+    const int n = s.n;
+    // (C-style casts: the only casts that change the address space)
+    const GlbPtr<const float> irow =
+        kPher == MMAS_PHER_DENSE ? (GlbPtr<const float>)(vw.choice_inv + (size_t)cur * n) : nullptr;
+    const GlbPtr<const int32_t> drow =
+        kPher == MMAS_PHER_DENSE ? nullptr : (GlbPtr<const int32_t>)(vw.dist + (size_t)cur * n);
+    const LdsPtr<const uint16_t> lv = (LdsPtr<const uint16_t>)tabu.list();
+    return fallback_half<kTabu, kPher>(lv, lv, L, n, irow, drow, tmin_a, s.beta, s.cl, s.seed, it, (uint32_t)ant,
+                                       (uint32_t)k, part, 2, lane);
 }
 
-// The helper wave of ant `ant`: buffers buf0 / buf1 (256 floats each, laid
-// out as the single colony's draw buffer), counters cnt[0] (groups written)
-// and cnt[1] (groups read).
-template <int kG>
-__device__ void draw_helper(const Shape& s, uint32_t it, int ant, int lane, float* buf0, float* buf1, int* cnt) {
+// The helper wave of ant `ant`: `region` is the ant's region (draw buffer 0
+// at its start, the tabu after it), `help` the helper's part (draw buffer 1,
+// then the HelpLds).
+template <int kTabu, int kPher, int kG>
+__device__ void draw_helper(const Views& vw, const Shape& s, uint32_t it, int ant, int lane, uint8_t* region,
+                            uint8_t* help) {
     constexpr int gsh = kG == 1 ? 0 : kG == 2 ? 1 : kG == 4 ? 2 : kG == 8 ? 3 : 4;
     constexpr int S = kWave >> gsh;
-    const int groups = (s.n + S - 1) / S;
+    const int n = s.n;
+    float* buf0 = reinterpret_cast<float*>(region);
+    float* buf1 = reinterpret_cast<float*>(help);
+    HelpLds* h = reinterpret_cast<HelpLds*>(help + kDrawBytes);
+    typename TabuOf<kTabu>::type tabu;
+    tabu.attach(region + kDrawBytes + kScratchBytes, n);
+    float tmin_a = 0.0f;
+    if (kHelpShare<kTabu> && kPher == MMAS_PHER_CANDIDATES) tmin_a = powi(vw.state->tau_min, s.alpha);
+    int served = 0;
+    // keys part 1 of a posted fallback, if there is one; true if it did
+    auto serve = [&]() -> bool {
+        if constexpr (!kHelpShare<kTabu>) {
+            return false;
+        } else {
+            const int r = lds_get(&h->req);
+            if (r <= served) return false;
+            asm volatile("" ::: "memory");
+            const unsigned long long res =
+                half_part<kTabu, kPher>(vw, s, it, ant, lds_get(&h->k), (uint32_t)lds_get(reinterpret_cast<int*>(&h->cur)),
+                                        lds_get(&h->L), tabu, tmin_a, 1, lane);
+            asm volatile("" ::: "memory");
+            *(LdsPtr<volatile unsigned long long>)&h->res = res;
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the result is in LDS before the count
+            lds_put(&h->done, r);
+            served = r;
+            return true;
+        }
+    };
+    // waits until the counter c reaches `want`, serving fallbacks meanwhile;
+    // false if it gave up
+    auto wait_serving = [&](const int* c, int want) -> bool {
+        for (int spins = 0; spins < kHelpSpins; ++spins) {
+            if (serve()) spins = 0;
+            if (lds_get(c) >= want) {
+                asm volatile("" ::: "memory");
+                return true;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        return false;
+    };
+    const int groups = (n + S - 1) / S;
     for (int g = 0; g < groups; ++g) {
         const Words4 b = draw_block(s.seed, it, (uint32_t)ant, (uint32_t)(g * S + (lane >> gsh)),
                                     (uint32_t)(4 * (lane & (kG - 1))));
@@ -713,12 +896,16 @@ __device__ void draw_helper(const Shape& s, uint32_t it, int ant, int lane, floa
         lv.y = log_u01(u01(b.w[1]));
         lv.z = log_u01(u01(b.w[2]));
         lv.w = log_u01(u01(b.w[3]));
+        // (computed before the wait, so that the waits serve fallbacks at once)
+        asm volatile("" : "+v"(lv.x), "+v"(lv.y), "+v"(lv.z), "+v"(lv.w));
         // the buffer of group g held group g - 2
-        if (g >= 2 && !wait_count(cnt + 1, g - 1)) return;
+        if (g >= 2 && !wait_serving(&h->read, g - 1)) return;
         *reinterpret_cast<float4*>(((g & 1) ? buf1 : buf0) + 4 * lane) = lv;
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the draws are in LDS before the count
-        post_count(cnt, g + 1);
+        lds_put(&h->made, g + 1);
     }
+    // every group is written: serve fallbacks until the tour is done
+    wait_serving(&h->stop, 1);
 }
 
 // One ant's tour (one wave64, the batched kernel's step): start city, n - 1
@@ -870,8 +1057,8 @@ __device__ void construct_ant(const Views& vw, const Shape& s, uint32_t it, int 
 // argmax reduces only the two rows that hold the list.
 // kWide: the wave leads a workgroup whose other waves share its fallbacks
 // (wide_helpers), nw waves in all. kHelp (kG > 0): a draw helper wave
-// (draw_helper) fills the draw buffers; `help` is its part of the region
-// (second buffer, counters).
+// (draw_helper) fills the draw buffers and keys half of every fallback;
+// `help` is its part of the region (second buffer, counters).
 template <int kTabu, int kPher, int kRows, int kG, bool kWide = false, bool kHelp = false>
 __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int ant, int lane, uint8_t* region,
                                const uint16_t* tcand, const float* tchc, int R, WideLds* wl = nullptr,
@@ -926,6 +1113,8 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
     int cur = start;
     bool bad = false;
     bool bad_help = false;  // a wait for the draw helper gave up
+    int fseq = 0;           // fallbacks posted to the helper
+    HelpLds* hl = kHelp ? reinterpret_cast<HelpLds*>(help + kDrawBytes) : nullptr;
 
     // the all-city fallback of step k from city cur (rare with a list)
     auto fallback = [&](int k) -> uint32_t {
@@ -938,22 +1127,45 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
             asm volatile("" : "+s"(kk));
         fb_steps += 1;
         fb_nodes += n - kk;
-        // (C-style casts: the only casts that change the address space)
-        const GlbPtr<const float> irow =
-            kPher == MMAS_PHER_DENSE ? (GlbPtr<const float>)(vw.choice_inv + (size_t)cur * n) : nullptr;
-        const GlbPtr<const int32_t> drow =
-            kPher == MMAS_PHER_DENSE ? nullptr : (GlbPtr<const int32_t>)(dist + (size_t)cur * n);
         uint32_t pick;
-        if constexpr (kWide)
+        if constexpr (kWide) {
             pick = wide_lead_fallback<kTabu, kPher>(vw, s, it, ant, kk, (uint32_t)cur, tabu, ulist, wl, tmin_a, lane, nw);
-        else if constexpr (kTabu == MMAS_TABU_BITMASK)
-            pick = fallback_lone<kTabu, kPher>((LdsPtr<const uint16_t>)tabu.bits, (LdsPtr<uint16_t>)ulist, n - kk, n,
-                                               irow, drow, tmin_a, s.beta, cl, seed, it, (uint32_t)ant, (uint32_t)k,
-                                               lane);
-        else
-            pick = fallback_lone<kTabu, kPher>((LdsPtr<const uint16_t>)tabu.list(), (LdsPtr<uint16_t>)tabu.list(), tabu.L,
-                                               n, irow, drow, tmin_a, s.beta, cl, seed, it, (uint32_t)ant, (uint32_t)k,
-                                               lane);
+        } else {
+            int L = n - kk;
+            if constexpr (kTabu != MMAS_TABU_BITMASK) L = tabu.L;
+            if constexpr (kHelp && kHelpShare<kTabu>) {
+                // post the fallback, key part 0 and take the better of the parts
+                ++fseq;
+                *reinterpret_cast<int4*>(&hl->k) = make_int4(kk, cur, L, 0);
+                asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");  // the record is in LDS before the count
+                lds_put(&hl->req, fseq);
+                const unsigned long long r0 =
+                    half_part<kTabu, kPher>(vw, s, it, ant, kk, (uint32_t)cur, L, tabu, tmin_a, 0, lane);
+                unsigned long long r1;
+                if (!bad_help && wait_count(&hl->done, fseq)) {
+                    r1 = *(LdsPtr<volatile unsigned long long>)&hl->res;
+                } else {  // (never expected) part 1 here too
+                    bad_help = true;
+                    r1 = half_part<kTabu, kPher>(vw, s, it, ant, kk, (uint32_t)cur, L, tabu, tmin_a, 1, lane);
+                }
+                const unsigned long long r = r0 > r1 ? r0 : r1;
+                pick = r ? ~(uint32_t)r : kNone;
+            } else {
+                // (C-style casts: the only casts that change the address space)
+                const GlbPtr<const float> irow =
+                    kPher == MMAS_PHER_DENSE ? (GlbPtr<const float>)(vw.choice_inv + (size_t)cur * n) : nullptr;
+                const GlbPtr<const int32_t> drow =
+                    kPher == MMAS_PHER_DENSE ? nullptr : (GlbPtr<const int32_t>)(dist + (size_t)cur * n);
+                if constexpr (kTabu == MMAS_TABU_BITMASK)
+                    pick = fallback_lone<kTabu, kPher>((LdsPtr<const uint16_t>)tabu.bits, (LdsPtr<uint16_t>)ulist, L,
+                                                       n, irow, drow, tmin_a, s.beta, cl, seed, it, (uint32_t)ant,
+                                                       (uint32_t)k, lane);
+                else
+                    pick = fallback_lone<kTabu, kPher>((LdsPtr<const uint16_t>)tabu.list(),
+                                                       (LdsPtr<uint16_t>)tabu.list(), L, n, irow, drow, tmin_a,
+                                                       s.beta, cl, seed, it, (uint32_t)ant, (uint32_t)k, lane);
+            }
+        }
         const uint32_t next = (uint32_t)__builtin_amdgcn_readfirstlane((int)pick);
         // no city is unreachable with a validated instance; were it not,
         // report it after the tour and go on with city 0 (the tour is void)
@@ -1065,18 +1277,18 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
         // draws from the helper wave: group g in buffer g & 1
         const LdsPtr<const float> buf0 = (LdsPtr<const float>)lnbuf;
         const LdsPtr<const float> buf1 = (LdsPtr<const float>)reinterpret_cast<float*>(help);
-        int* cnt = reinterpret_cast<int*>(help + kDrawBytes);
         constexpr int S = kWave / kG;
         load_row(cur);
         int g = 0;
         for (int k0 = 0; k0 < n; k0 += S, ++g) {
-            if (!bad_help) bad_help = !wait_count(cnt, g + 1);  // (after one timeout, no more waits)
+            if (!bad_help) bad_help = !wait_count(&hl->made, g + 1);  // (after one timeout, no more waits)
             lds_ln = (g & 1) ? buf1 : buf0;
             const int ke = k0 + S < n ? k0 + S : n;
             steps_plain(k0, k0 > 0 ? k0 : 1, ke);
-            post_count(cnt + 1, g + 1);  // after the group's last read of its buffer
+            lds_put(&hl->read, g + 1);  // after the group's last read of its buffer
             flush(ke);
         }
+        lds_put(&hl->stop, 1);
     } else if constexpr (kG > 0) {
         load_row(cur);
         // Draws computed one group ahead, spread over the steps of the group
@@ -1400,10 +1612,12 @@ __global__ __launch_bounds__(1024) void k_construct(Views vw, Shape s, uint32_t 
     uint8_t* regions = smem + lds.table_bytes;
     if (R > 0) stage_table(vw, s.cl, R, tcand, tchc);
     if constexpr (kHelp) {
-        // both counters of every ant start at 0
-        if ((int)threadIdx.x < ants_per_block)
-            *reinterpret_cast<int2*>(regions + (size_t)(threadIdx.x + 1) * lds.per_ant - kHelpBytes + kDrawBytes) =
-                make_int2(0, 0);
+        // every ant's HelpLds starts at 0 (three 16-byte stores each)
+        if ((int)threadIdx.x < 3 * ants_per_block) {
+            const int a = (int)threadIdx.x / 3, q = (int)threadIdx.x % 3;
+            *reinterpret_cast<int4*>(regions + (size_t)(a + 1) * lds.per_ant - sizeof(HelpLds) + 16 * q) =
+                make_int4(0, 0, 0, 0);
+        }
     }
     if (R > 0 || kHelp) __syncthreads();
     const bool helper = kHelp && wave >= ants_per_block;
@@ -1414,8 +1628,7 @@ __global__ __launch_bounds__(1024) void k_construct(Views vw, Shape s, uint32_t 
         uint8_t* region = regions + (size_t)aw * lds.per_ant;
         uint8_t* help = region + lds.per_ant - kHelpBytes;
         if (helper)
-            draw_helper<kG>(s, it, ant, lane, reinterpret_cast<float*>(region), reinterpret_cast<float*>(help),
-                            reinterpret_cast<int*>(help + kDrawBytes));
+            draw_helper<kTabu, kPher, kG>(vw, s, it, ant, lane, region, help);
         else
             construct_lone<kTabu, kPher, kRows, kG, false, true>(vw, s, it, ant, lane, region, tcand, tchc, R,
                                                                  nullptr, 1, help);
