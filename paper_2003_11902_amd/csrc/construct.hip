@@ -1192,7 +1192,7 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
     // The row entry of this lane for city c (rank lr of its candidate list),
     // loaded one step ahead: as soon as the next city is known, before it is
     // marked, so the loads are not queued behind the mark.
-    uint32_t node_next = 0;
+    uint16_t node_next = 0;  // (16 bits: widened where it is used, not where the loads meet)
     float w_next = 0.0f;
     auto load_row = [&](int c) {
         const int e = c * cl + lr;
