@@ -1096,13 +1096,13 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
     const int lr = lane < cl ? lane : cl - 1;       // lanes past the list repeat the last entry
     const uint32_t lane_ok = lane < cl ? ~0u : 0u;  // ... and never hold a key
     const int ln_lane = lane & (4 * G - 1);
-    // bitmask marks: byte offset of each lane's OR (see below)
-    uint32_t mark_is0 = lane == 0 ? 1u : 0u;
+    // bitmask marks: LDS byte address of each lane's OR (see below)
     uint32_t mark_mask = lane == 0 ? ~0u : 0u;
-    uint32_t mark_base = lane == 0 ? (uint32_t)(kDrawBytes + kScratchBytes) : 4u * (uint32_t)lane;  // from region
+    uint32_t mark_base = (uint32_t)(uintptr_t)(LdsPtr<uint8_t>)region +
+                         (lane == 0 ? (uint32_t)(kDrawBytes + kScratchBytes) : 4u * (uint32_t)lane);
     // (opaque to the compiler, which would otherwise turn the arithmetic
     // below back into lane-0 selects)
-    asm volatile("" : "+v"(mark_is0), "+v"(mark_mask), "+v"(mark_base));
+    asm volatile("" : "+v"(mark_mask), "+v"(mark_base));
 
     uint16_t* tour_out = vw.tours + (size_t)ant * n;
     const int32_t* dist = vw.dist;
@@ -1180,8 +1180,9 @@ __device__ void construct_lone(const Views& vw, const Shape& s, uint32_t it, int
             // every lane issues the OR, so that no exec mask is set up around
             // it: lane 0 into the city's word, the others a 0 into their own
             // word of the draw buffer (no change)
-            const uint32_t off = mark_base + mark_is0 * ((next >> 5) << 2);
-            atomicOr(reinterpret_cast<uint32_t*>(region + off), (1u << (next & 31u)) & mark_mask);
+            const uint32_t addr = mark_base + (((next >> 5) << 2) & mark_mask);
+            __hip_atomic_fetch_or((LdsPtr<uint32_t>)(uintptr_t)addr, (1u << (next & 31u)) & mark_mask,
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         } else {
             tabu.mark(next, lane);
         }
