@@ -179,11 +179,14 @@ mmas_status mmas_construct(mmas_ctx* ctx, uint32_t iteration);
  * steps, all of them share every all-city fallback; ignored with 32 lanes
  * per ant); 0 (default): several only where the all-city fallback dominates
  * (n >= 8192: the largest power of two up to 16 such that ants x waves fit
- * the GPU's SIMDs once; no candidate list with the compact or list tabu and
- * n >= 512: 4), else 1; and where that is one wave with 9 <= cand_len <= 32
- * and at most as many ants as the GPU has SIMDs, a second wave per ant
- * computes the steps' draws ahead into LDS (a draw helper; at most 8 ants per
- * workgroup then). 1 = the ant's wave alone. EINVAL for other values. */
+ * the GPU's SIMDs once; no candidate list and n >= 512: 4), else 1; and
+ * where that is one wave with 9 <= cand_len <= 32 and at most as many ants
+ * as the GPU has SIMDs, a second wave per ant computes the steps' draws
+ * ahead into LDS (a draw helper; at most 8 ants per workgroup then).
+ * 1 = the ant's wave alone. Without a candidate list, with the bitmask
+ * tabu and n <= 1024, four waves per ant (by default or asked for) form a
+ * team that splits every step's keys (one barrier a step). EINVAL for other
+ * values. */
 mmas_status mmas_set_launch(mmas_ctx* ctx, int32_t ants_per_block, int32_t table_rows, int32_t lanes_per_ant,
                             int32_t waves_per_ant);
 

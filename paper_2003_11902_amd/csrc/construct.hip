@@ -1919,10 +1919,10 @@ hipError_t launch_t(const Views& v, const Shape& s0, uint32_t it, hipStream_t st
 // where the all-city fallback dominates the step, the only part the helper
 // waves share. With n >= 8192 (long fallbacks) and SIMDs to spare: as many
 // as the SIMDs left over by one wave per ant allow, a power of two up to 16.
-// Without a candidate list and with a tabu that keeps the unvisited cities
-// listed (compact, list) at n >= 512: four. Otherwise one: the per-step
-// barriers then cost more than the shared fallbacks save (measured at
-// n = 198, 1002 and 3795 with and without lists).
+// Without a candidate list at n >= 512: four (the bitmask tabu's cities are
+// then gathered by the workgroup, one LDS atomic per wave). Otherwise one:
+// the per-step barriers then cost more than the shared fallbacks save
+// (measured at n = 198, 1002 and 3795 with and without lists).
 int construct_waves(const Shape& s) {
     if (s.construct_waves > 0) return s.construct_waves;
     if (s.n >= 8192) {
@@ -1932,7 +1932,7 @@ int construct_waves(const Shape& s) {
         while (w < 16 && 2 * w * s.ants <= simds) w *= 2;
         return w;
     }
-    if (s.cl == 0 && s.tabu != MMAS_TABU_BITMASK && s.n >= 512) return 4;
+    if (s.cl == 0 && s.n >= 512) return 4;
     return 1;
 }
 
@@ -1967,13 +1967,12 @@ hipError_t launch_wide(const Views& v, const Shape& s, uint32_t it, int waves, h
 }
 
 // The team kernel (four waves per ant, no list, bitmask tabu, n <= 1024):
-// asked for with four waves per ant, or by default while every ant's four
-// waves find SIMDs of their own.
+// by default, or asked for with four waves per ant. Measured at n = 1002
+// with 1002 ants (four waves per SIMD): 2.55 ms against 2.92 ms with four
+// waves sharing the fallbacks and 3.06 ms with one wave per ant.
 bool team_ok(const Shape& s) {
     if (s.cl != 0 || s.tabu != MMAS_TABU_BITMASK || s.n > 1024 || s.select != MMAS_SELECT_WRS) return false;
-    if (s.construct_waves > 0) return s.construct_waves == 4;
-    const int simds = device_attr(g_simds, hipDeviceAttributeMultiprocessorCount, 4, 0);
-    return 4 * s.ants <= simds;
+    return s.construct_waves == 0 || s.construct_waves == 4;
 }
 
 template <int kPher>

@@ -255,7 +255,7 @@ def test_roulette_wheel_needs_bitmask(gpu):
     assert e.value.status == M.MMAS_EUNSUPPORTED
 
 
-@pytest.mark.parametrize("tabu", ["list", "compact"])
+@pytest.mark.parametrize("tabu", ["list", "compact", "bitmask"])
 @pytest.mark.parametrize("cl,waves,pher", [(0, 0, "dense"), (0, 16, "dense"), (1, 4, "dense"), (3, 2, "candidates"),
                                              (0, 1, "dense"), (2, 1, "candidates")])
 def test_wide_fallback_by_draw_blocks(gpu, tabu, cl, waves, pher):
@@ -269,15 +269,16 @@ def test_wide_fallback_by_draw_blocks(gpu, tabu, cl, waves, pher):
 
 
 @pytest.mark.parametrize("n,pher,ants,waves", [(257, "dense", 40, 0), (1021, "dense", 20, 4),
-                                               (64, "dense", 300, 4), (5, "dense", 3, 0), (1024, "dense", 8, 0)])
+                                               (64, "dense", 300, 4), (5, "dense", 3, 0), (1024, "dense", 8, 0),
+                                               (600, "dense", 300, 0)])
 def test_team_without_list(gpu, n, pher, ants, waves):
     """No candidate list, bitmask tabu, n <= 1024: the team launch (four waves
     per ant, one word of every draw block each, visited bits in registers) is
-    taken by default while four waves per ant fit the SIMDs, or with four
-    waves asked for; tours, lengths, fallback counts and trails equal the
-    oracle's. The sizes cover a partial last round of blocks (257), four
-    rounds (1021, 1024), one partial round (64, 5) and more ants than the
-    default would give four waves (300)."""
+    taken by default or with four waves asked for; tours, lengths, fallback
+    counts and trails equal the oracle's. The sizes cover a partial last
+    round of blocks (257), four rounds (1021, 1024), one partial round (64,
+    5), and more ants than SIMDs hold four waves each (300 ants: 1200 waves,
+    asked for and by default)."""
     _, d = I.make_instance("uniform", n, seed=n + 3, side=1e5)
     say(f"team no list n={n} {pher} ants={ants} waves={waves}")
     run_parity(d, 3, ants=ants, cand_len=0, rho=0.1, seed=4, tabu="bitmask", pher=pher, launch=(0, -1, 64, waves))
