@@ -76,10 +76,13 @@ struct CompactTabu {
     __device__ __forceinline__ uint32_t live(uint32_t v) const { return entries[v] > v ? 0u : ~0u; }
     __device__ __forceinline__ const uint16_t* list() const { return entries; }  // the L unvisited cities
     __device__ __forceinline__ void mark(uint32_t u, int lane) {
-        // every lane reads the same cells; lane 0 writes
-        const int iu = entries[u];  // position of u in the left part
+        // u is wave-uniform: both cells are read at once (the same for every
+        // lane, one LDS round trip) into scalar registers; lane 0 writes
+        const int iu_v = entries[u];     // position of u in the left part
+        const int t_v = entries[L - 1];  // last city of the left part
+        const int iu = __builtin_amdgcn_readfirstlane(iu_v);
+        const int t = __builtin_amdgcn_readfirstlane(t_v);
         L = L - 1;
-        const int t = entries[L];   // last city of the left part
         if (lane == 0) {
             if (iu == L) {
                 entries[L] = (uint16_t)n;
