@@ -779,9 +779,11 @@ __device__ void wide_lead_end(WideLds* wl, int lane) {
 // (kHelpShare) it also keys half of every all-city fallback (fallback_half's
 // part 1) while the ant's wave keys the other half. Counters in LDS hand the
 // buffers and the fallbacks over: the helper writes group g once group
-// g - 2 is read, and serves a posted fallback whenever it waits. Waits are bounded: past the limit the ant's
-// wave flags the tour (state flag 32) and keys the rest alone, and the
-// helper leaves, so no wave can wait for ever.
+// g - 2 is read, and serves a posted fallback whenever it waits. Waits are
+// bounded: past the limit the ant's wave flags the tour (state flag 32) and
+// keys the rest alone, and the helper leaves, so no wave can wait for ever.
+// Both waves must read any counter the other writes through lds_get (a
+// volatile LDS read) and write their own through lds_put.
 struct HelpLds {
     int made;                // draw groups written (helper)
     int read;                // draw groups read (ant's wave)
@@ -792,15 +794,14 @@ struct HelpLds {
     int L;                   // unvisited cities,
     int stop;                // and 1 once the tour is done (the helper leaves)
     unsigned long long res;  // part 1's best (share_result) of fallback `done`
-    int pad[2];
+    int pad[2];              // (to 48 bytes)
 };
 static_assert(sizeof(HelpLds) == 48, "16-byte multiple");
 constexpr size_t kHelpBytes = kDrawBytes + sizeof(HelpLds);  // second draw buffer, then the counters
 constexpr int kHelpSpins = 1 << 24;                          // sleeps of 64 clocks before a wait gives up
 // The tabus whose fallbacks the helper shares: measured at n = 1002, the
-// shared fallback made the compact tabu's construction 4 % faster and the
-// bitmask and list tabus' 1-3 % slower (the bitmask keeps its one-pass
-// listing, the list tabu's fallbacks are short).
+// shared fallback made the compact tabu's construction about 7 % faster; the
+// bitmask tabu's it made 1-3 % slower and the list tabu's no faster.
 template <int kTabu>
 constexpr bool kHelpShare = kTabu == MMAS_TABU_COMPACT;
 
